@@ -1,0 +1,200 @@
+"""Seeded synthetic inputs: graphs, log-factor tables, unaries and churn batches.
+
+This module holds no arithmetic of the sampler.  It is the only code that both
+the GPU path (bench, tests) and the CPU oracle (tests) consume.  Every generator
+draws from ``numpy.random.default_rng(seed)`` in a fixed order, stated in each
+docstring, so the same seed gives the same model everywhere.
+
+Conventions (the paper's experiments, Sec. 6, define the workload families):
+  * node states x in {0..q-1}; Ising spins s = 2x - 1;
+  * ``Lam[e][a][b]`` = log phi_e(x_src = a, x_dst = b), row = src state;
+  * ``lam[i][a]`` = log u_i(a);
+  * entries beyond a node's q are zero and never read;
+  * N(mu, s) means standard deviation s.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Model:
+    q: np.ndarray          # int32 [n]
+    lam: np.ndarray        # [n][q_max], dtype = table precision
+    src: np.ndarray        # int32 [m]
+    dst: np.ndarray        # int32 [m]
+    Lam: np.ndarray        # [m][q_max][q_max], dtype = table precision
+    name: str = "model"
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.q.shape[0])
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+    @property
+    def q_max(self) -> int:
+        return int(self.lam.shape[1])
+
+    @property
+    def fp64(self) -> bool:
+        return self.Lam.dtype == np.float64
+
+    def subset_edges(self, idx) -> "Model":
+        idx = np.asarray(idx)
+        return Model(self.q, self.lam, self.src[idx], self.dst[idx], self.Lam[idx],
+                     self.name, dict(self.meta))
+
+
+def _np_dtype(dtype: str):
+    return {"f32": np.float32, "f64": np.float64}[dtype]
+
+
+def grid_edges(H: int, W: int):
+    """Open-boundary 4-neighbour grid, node = r*W + c.  All horizontal edges in
+    row-major order, then all vertical ones; src is the left/top endpoint."""
+    r, c = np.meshgrid(np.arange(H), np.arange(W - 1), indexing="ij")
+    hs = (r * W + c).ravel()
+    hd = hs + 1
+    r, c = np.meshgrid(np.arange(H - 1), np.arange(W), indexing="ij")
+    vs = (r * W + c).ravel()
+    vd = vs + W
+    return (np.concatenate([hs, vs]).astype(np.int32),
+            np.concatenate([hd, vd]).astype(np.int32))
+
+
+def ising_grid(H: int, W: int, seed: int = 0, J_half_range: float = 0.3,
+               h_std: float = 0.5, dtype: str = "f64") -> Model:
+    """Binary grid with phi_e = exp(J_e s_i s_j), u_i = exp(h_i s_i).
+    Draw order: J_e ~ U(-J_half_range, J_half_range) for every edge, then
+    h_i ~ N(0, h_std) for every node."""
+    rng = np.random.default_rng(seed)
+    src, dst = grid_edges(H, W)
+    J = rng.uniform(-J_half_range, J_half_range, size=src.shape[0])
+    h = rng.normal(0.0, h_std, size=H * W)
+    return ising_model(src, dst, J, h, H * W, dtype, name=f"ising_grid_{H}x{W}")
+
+
+def ising_model(src, dst, J, h, n, dtype="f64", name="ising") -> Model:
+    s = np.array([-1.0, 1.0])
+    Lam = J[:, None, None] * s[None, :, None] * s[None, None, :]
+    lam = h[:, None] * s[None, :]
+    dt = _np_dtype(dtype)
+    return Model(np.full(n, 2, np.int32), lam.astype(dt), np.asarray(src, np.int32),
+                 np.asarray(dst, np.int32), Lam.astype(dt), name)
+
+
+def table_grid(H: int, W: int, q: int, seed: int = 0, pair_std: float = 0.2,
+               unary_std: float = 1.0, dtype: str = "f32") -> Model:
+    """q-state grid with iid Gaussian log-tables.  Draw order: Lam [m][q][q]
+    ~ N(0, pair_std), then lam [n][q] ~ N(0, unary_std); generated in the table
+    precision."""
+    rng = np.random.default_rng(seed)
+    src, dst = grid_edges(H, W)
+    dt = _np_dtype(dtype)
+    Lam = (rng.standard_normal((src.shape[0], q, q), dtype=dt) * dt(pair_std)).astype(dt)
+    lam = (rng.standard_normal((H * W, q), dtype=dt) * dt(unary_std)).astype(dt)
+    return Model(np.full(H * W, q, np.int32), lam, src, dst, Lam, f"grid_{H}x{W}_q{q}")
+
+
+def chung_lu_weights(n: int, gamma: float = 2.5, mean_deg: float = 8.0) -> np.ndarray:
+    """Expected degrees w_i proportional to (i + i0)^(-1/(gamma-1)), scaled to
+    mean ``mean_deg``, with i0 chosen so that w_0 = sqrt(sum w)."""
+    alpha = 1.0 / (gamma - 1.0)
+    i = np.arange(n, dtype=np.float64)
+    target = np.sqrt(n * mean_deg)
+
+    def w0(i0):
+        base = (i + i0) ** (-alpha)
+        return n * mean_deg * base[0] / base.sum()
+
+    lo, hi = 1e-6, float(n)
+    for _ in range(200):
+        mid = np.sqrt(lo * hi)
+        if w0(mid) > target:
+            lo = mid
+        else:
+            hi = mid
+    i0 = np.sqrt(lo * hi)
+    base = (i + i0) ** (-alpha)
+    return n * mean_deg * base / base.sum()
+
+
+def chung_lu(n: int, q: int, seed: int = 0, gamma: float = 2.5, mean_deg: float = 8.0,
+             pair_std: float = 0.15, unary_std: float = 1.0, dtype: str = "f32") -> Model:
+    """Chung-Lu power-law graph.  Draw order: M = round(n mean_deg / 2) src
+    endpoints iid proportional to w, then M dst endpoints; self-loops and repeated
+    unordered pairs are dropped (first occurrence kept, draw order preserved);
+    then Lam [m][q][q] ~ N(0, pair_std), then lam [n][q] ~ N(0, unary_std)."""
+    rng = np.random.default_rng(seed)
+    w = chung_lu_weights(n, gamma, mean_deg)
+    p = w / w.sum()
+    M = int(round(n * mean_deg / 2))
+    s = rng.choice(n, size=M, p=p)
+    d = rng.choice(n, size=M, p=p)
+    keep = s != d
+    s, d = s[keep], d[keep]
+    key = np.minimum(s, d).astype(np.int64) * n + np.maximum(s, d)
+    _, first = np.unique(key, return_index=True)
+    first.sort()
+    src, dst = s[first].astype(np.int32), d[first].astype(np.int32)
+    dt = _np_dtype(dtype)
+    Lam = (rng.standard_normal((src.shape[0], q, q), dtype=dt) * dt(pair_std)).astype(dt)
+    lam = (rng.standard_normal((n, q), dtype=dt) * dt(unary_std)).astype(dt)
+    return Model(np.full(n, q, np.int32), lam, src, dst, Lam, f"chung_lu_{n}_q{q}",
+                 {"weights": w})
+
+
+def random_graph(n: int, m: int, qs, seed: int = 0, pair_std: float = 0.5,
+                 unary_std: float = 1.0, dtype: str = "f64", allow_parallel=True) -> Model:
+    """Small mixed-q test graph.  Draw order: q_i uniform from ``qs`` for every
+    node, then m (src, dst) pairs uniform without self-loops (dst redrawn as
+    (src + 1 + U{0..n-2}) mod n), then Lam, then lam, all N(0, std)."""
+    rng = np.random.default_rng(seed)
+    q = rng.choice(np.asarray(qs), size=n).astype(np.int32)
+    qm = int(max(qs))
+    src = rng.integers(0, n, size=m)
+    dst = (src + 1 + rng.integers(0, n - 1, size=m)) % n
+    dt = _np_dtype(dtype)
+    Lam = rng.normal(0.0, pair_std, size=(m, qm, qm))
+    lam = rng.normal(0.0, unary_std, size=(n, qm))
+    for e in range(m):
+        Lam[e, q[src[e]]:, :] = 0.0
+        Lam[e, :, q[dst[e]]:] = 0.0
+    for i in range(n):
+        lam[i, q[i]:] = 0.0
+    return Model(q, lam.astype(dt), src.astype(np.int32), dst.astype(np.int32),
+                 Lam.astype(dt), f"random_{n}_{m}")
+
+
+class Churn:
+    """Edge churn for dynamic graphs: each batch removes ``frac`` of the live
+    edges uniformly without replacement and inserts as many new edges whose
+    endpoints are drawn iid proportional to ``weights`` (a self-loop's dst is
+    moved to the next node), with fresh tables Lam ~ N(0, pair_std).
+    Draw order per batch: removal positions, src, dst, tables."""
+
+    def __init__(self, n: int, q: int, weights, seed: int = 1, frac: float = 0.01,
+                 pair_std: float = 0.15, dtype: str = "f32"):
+        self.rng = np.random.default_rng(seed)
+        self.n, self.q, self.frac, self.pair_std = n, q, frac, pair_std
+        w = np.asarray(weights, np.float64)
+        self.p = w / w.sum()
+        self.dt = _np_dtype(dtype)
+
+    def next_batch(self, live_uids: np.ndarray):
+        """live_uids: the live edges in a fixed order.  Returns (remove_uids,
+        src, dst, Lam) for the batch."""
+        k = int(round(self.frac * len(live_uids)))
+        pos = np.sort(self.rng.choice(len(live_uids), size=k, replace=False))
+        s = self.rng.choice(self.n, size=k, p=self.p)
+        d = self.rng.choice(self.n, size=k, p=self.p)
+        d = np.where(s == d, (d + 1) % self.n, d)
+        Lam = (self.rng.standard_normal((k, self.q, self.q), dtype=self.dt)
+               * self.dt(self.pair_std)).astype(self.dt)
+        return (np.asarray(live_uids)[pos], s.astype(np.int32), d.astype(np.int32), Lam)
