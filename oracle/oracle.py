@@ -89,6 +89,11 @@ def _declare(L):
     L.orc_run.argtypes = [_I64, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _U64,
                           _U32, _I64, _I64, _P, _P, _P, _P]
     L.orc_run.restype = ctypes.c_int
+    L.orc_primal_phase.argtypes = [_I64, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _U64,
+                                   _U32, _P, _P, _P]
+    L.orc_primal_phase.restype = ctypes.c_int
+    L.orc_num_threads.argtypes = []
+    L.orc_num_threads.restype = ctypes.c_int
     L.orc_all_logits.argtypes = [_I64, _I64, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_all_logits.restype = ctypes.c_int
 
@@ -157,6 +162,10 @@ def decompose(model) -> Decomposition:
     return Decomposition(par, rrow, rcol)
 
 
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
 # ------------------------------------------------------------------------ sweeps
 def init_state(model, C, seed) -> np.ndarray:
     q, pq = _c(model.q, np.int32)
@@ -196,6 +205,23 @@ def sweep(model, dec, uid, seed, t, x_in):
     if rc != 0:
         raise MemoryError("oracle sweep failed")
     return theta, dflag, x_out, pflag
+
+
+def primal_phase(model, dec, seed, t, theta):
+    """Primal phase of sweep t from given duals theta [m][C] (u64 bit d):
+    returns (x_out [n][C] u8, pflag [n][C] u8)."""
+    theta = np.ascontiguousarray(theta, np.uint64)
+    C = theta.shape[1] if theta.ndim == 2 else 1
+    x_out = np.zeros((model.n, C), np.uint8)
+    pflag = np.zeros((model.n, C), np.uint8)
+    args, keep = _graph_args(model, dec, np.zeros(model.m, np.uint64))
+    a = [args[0], args[1], args[2], args[3], args[5], args[6], args[7]]
+    rc = lib().orc_primal_phase(model.n, model.m, C, model.q_max, *a, seed, t,
+                                theta.ctypes.data_as(_P), x_out.ctypes.data_as(_P),
+                                pflag.ctypes.data_as(_P))
+    if rc != 0:
+        raise MemoryError("oracle primal phase failed")
+    return x_out, pflag
 
 
 def run(model, dec, uid, seed, x, t0, n_sweeps, burn_in, counts=None):

@@ -44,6 +44,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PHASE_INIT 0u
 #define ORC_PHASE_DUAL 1u
@@ -129,7 +132,9 @@ void orc_factor2x2(const double P[4], double B[4], double C[4])
     double a = s12 / sqrt(s11 * s22);
     if (a > 1.0) a = 1.0;
     double cphi = 0.5 * (sqrt(1.0 + a) + sqrt(1.0 - a));
-    double sphi = 0.5 * (sqrt(1.0 + a) - sqrt(1.0 - a));
+    /* the Remark's sin = (sqrt(1+a) - sqrt(1-a)) / 2, multiplied through by the
+     * conjugate so that it does not cancel when a is small (strong coupling) */
+    double sphi = a / (sqrt(1.0 + a) + sqrt(1.0 - a));
     double r1 = sqrt(s11), r2 = sqrt(s22);
     double bt11 = r1 * cphi, bt12 = r1 * sphi, bt21 = r2 * sphi, bt22 = r2 * cphi;
     /* Undo the scaling: P = diag(p12, p21) S  =>  B = diag(p12, p21) Bt, C = Bt. */
@@ -495,6 +500,29 @@ int orc_sweep(int64_t n, int64_t m, int32_t C, int32_t q_max, const int32_t *q,
 }
 
 /*
+ * Primal phase of sweep t alone, from given duals theta [m][C] (teacher forcing
+ * of the node draws).  pflag may be NULL.
+ */
+int orc_primal_phase(int64_t n, int64_t m, int32_t C, int32_t q_max, const int32_t *q,
+                     const double *lam, const int32_t *src, const int32_t *dst,
+                     const double *par, const double *rrow, const double *rcol,
+                     uint64_t seed, uint32_t t, const uint64_t *theta, uint8_t *x_out,
+                     uint8_t *pflag)
+{
+    orc_graph g = {n, m, C, q_max, q, lam, src, dst, 0, par, rrow, rcol, seed, 0, 0, 0};
+    if (orc_graph_build(&g)) { orc_graph_free(&g); return -1; }
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int32_t c = 0; c < C; ++c) {
+        orc_scratch w = {0, 0, 0, 0, 0, 0};
+        err |= orc_primal_chain(&g, theta, c, t, x_out, pflag, &w) ? 1 : 0;
+        orc_scratch_free(&w);
+    }
+    orc_graph_free(&g);
+    return err ? -1 : 0;
+}
+
+/*
  * Free-running sweeps t0+1 .. t0+n_sweeps on x (in place).  After the primal
  * phase of sweep t, if t > burn_in, counts[i][x_i] += 1 for every chain.
  * n_flag_out (optional) receives the number of flagged draws (dual + primal),
@@ -570,4 +598,14 @@ int orc_all_logits(int64_t n, int64_t m, int32_t q_max, const int32_t *q,
     orc_scratch_free(&w);
     orc_graph_free(&g);
     return err ? -1 : 0;
+}
+
+/* Threads the OpenMP loops over chains use (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -1,0 +1,991 @@
+// libpdg: host runtime and C ABI of the primal-dual Gibbs sweep (include/pdg.h).
+//
+// The context owns every device buffer.  Sweeps are two kernels per sweep on
+// the caller's stream.  Edge edits are decided on the host -- a slot
+// allocator (free stack, generation-tagged uids) and per-node incidence
+// segments with slack -- and written to the device by small scatter kernels,
+// so an edit batch costs O(batch) plus an occasional segment relocation; no
+// colouring and no rebuild of the incidence lists is ever needed (the
+// abstract, Sec. 1 and Sec. 6 of the paper motivate the method by exactly
+// this setting).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pdg.h"
+#include "pdg_kernels.hpp"
+
+namespace pdg {
+
+static thread_local std::string g_global_err;
+
+struct Store {
+    int64_t S = 0;
+    std::vector<uint64_t> uid;     // [S], 0 = free
+    std::vector<uint32_t> gen;     // [S]
+    std::vector<int32_t> src, dst; // [S]
+    std::vector<uint32_t> pos0, pos1;
+    std::vector<int32_t> free_stack;
+    int64_t hwm = 0, live = 0;
+    std::vector<uint32_t> off, cnt, cap, nlive;  // per node
+    std::vector<uint32_t> pool;
+    int64_t pool_top = 0;
+};
+
+}  // namespace pdg
+
+struct pdg_ctx {
+    pdg_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int QM = 0, D = 0, C = 0, Wz = 0, LPI = 0, CB = 0;
+    int64_t bbytes = 0;
+    int64_t n = 0;
+    bool nodes_set = false;
+    int64_t t = 0;
+    int phase = 0;  // 0: between sweeps, 1: dual done
+    int64_t counted = 0;
+    // device
+    uint8_t *d_q = nullptr;
+    double *d_lam = nullptr;
+    uint8_t *d_x = nullptr;
+    uint32_t *d_counts = nullptr;
+    int32_t *d_src = nullptr, *d_dst = nullptr;
+    uint64_t *d_uid = nullptr;
+    uint8_t *d_sq = nullptr;
+    uint8_t *d_params = nullptr;
+    uint32_t *d_z = nullptr;
+    uint32_t *d_off = nullptr, *d_cnt = nullptr;
+    uint32_t *d_pool = nullptr;
+    int64_t dev_pool_cap = 0;
+    uint32_t *d_flag = nullptr;
+    void *d_scratch = nullptr;
+    int64_t scratch_bytes = 0;
+    pdg::Store st;
+    std::string err;
+};
+
+namespace pdg {
+
+static pdg_status fail(pdg_ctx *ctx, pdg_status code, const std::string &msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_global_err = msg;
+    return code;
+}
+
+#define PDG_HIP(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), PDG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define PDG_TRY(expr)                  \
+    do {                               \
+        pdg_status s_ = (expr);        \
+        if (s_ != PDG_OK) return s_;   \
+    } while (0)
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline unsigned grid_for(int64_t threads, int block = 256)
+{
+    return (unsigned)cdiv(std::max<int64_t>(threads, 1), block);
+}
+
+static int choose_lpi(int C)
+{
+    if (C >= 33) return 64;
+    if (C >= 17) return 32;
+    if (C >= 9) return 16;
+    if (C >= 2) return 8;
+    return 1;
+}
+
+static pdg_status dalloc(pdg_ctx *ctx, void **p, int64_t bytes)
+{
+    *p = nullptr;
+    if (bytes <= 0) return PDG_OK;
+    hipError_t e = hipMalloc(p, (size_t)bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(ctx, PDG_ENOMEM,
+                    "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    return PDG_OK;
+}
+
+static pdg_status scratch(pdg_ctx *ctx, int64_t bytes, void **out)
+{
+    if (bytes > ctx->scratch_bytes) {
+        if (ctx->d_scratch) PDG_HIP(ctx, hipFree(ctx->d_scratch));
+        ctx->d_scratch = nullptr;
+        ctx->scratch_bytes = 0;
+        int64_t want = std::max<int64_t>(bytes, 1 << 20);
+        PDG_TRY(dalloc(ctx, &ctx->d_scratch, want));
+        ctx->scratch_bytes = want;
+    }
+    *out = ctx->d_scratch;
+    return PDG_OK;
+}
+
+static pdg_status set_dev(pdg_ctx *ctx)
+{
+    PDG_HIP(ctx, hipSetDevice(ctx->device));
+    return PDG_OK;
+}
+
+static pdg_status read_flag(pdg_ctx *ctx, uint32_t *h)
+{
+    PDG_HIP(ctx, hipMemcpyAsync(h, ctx->d_flag, 4, hipMemcpyDeviceToHost, ctx->stream));
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PDG_OK;
+}
+
+static pdg_status clear_flag(pdg_ctx *ctx)
+{
+    k_fill_u32<<<1, 64, 0, ctx->stream>>>(ctx->d_flag, 1, 0u);
+    PDG_HIP(ctx, hipGetLastError());
+    return PDG_OK;
+}
+
+static Graph make_graph(pdg_ctx *ctx)
+{
+    Graph g;
+    g.q = ctx->d_q;
+    g.lam = ctx->d_lam;
+    g.src = ctx->d_src;
+    g.dst = ctx->d_dst;
+    g.uid = ctx->d_uid;
+    g.sq = ctx->d_sq;
+    g.params = ctx->d_params;
+    g.z = ctx->d_z;
+    g.inc_off = ctx->d_off;
+    g.inc_cnt = ctx->d_cnt;
+    g.inc = ctx->d_pool;
+    g.x = ctx->d_x;
+    g.counts = ctx->d_counts;
+    g.n = ctx->n;
+    g.hwm = ctx->st.hwm;
+    g.C = ctx->C;
+    g.Wz = ctx->Wz;
+    g.k0 = (uint32_t)ctx->cfg.seed;
+    g.k1 = (uint32_t)(ctx->cfg.seed >> 32);
+    return g;
+}
+
+// ------------------------------------------------------------- kernel dispatch
+template <int QM, int LPI>
+static void launch_dual_t(const Graph &g, uint32_t t, int CB, hipStream_t s)
+{
+    constexpr int P = 64 / LPI;
+    const int64_t waves = cdiv(g.hwm, P) * CB;
+    k_dual<QM, LPI><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+}
+
+template <int QM, int LPI, bool E64>
+static void launch_primal_t(const Graph &g, uint32_t t, int count, int CB, hipStream_t s)
+{
+    constexpr int P = 64 / LPI;
+    const int64_t waves = cdiv(g.n, P) * CB;
+    k_primal<QM, LPI, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
+}
+
+template <int QM>
+static void dual_q(int lpi, const Graph &g, uint32_t t, int CB, hipStream_t s)
+{
+    switch (lpi) {
+    case 1: launch_dual_t<QM, 1>(g, t, CB, s); break;
+    case 8: launch_dual_t<QM, 8>(g, t, CB, s); break;
+    case 16: launch_dual_t<QM, 16>(g, t, CB, s); break;
+    case 32: launch_dual_t<QM, 32>(g, t, CB, s); break;
+    default: launch_dual_t<QM, 64>(g, t, CB, s); break;
+    }
+}
+
+template <int QM, bool E64>
+static void primal_q(int lpi, const Graph &g, uint32_t t, int count, int CB, hipStream_t s)
+{
+    switch (lpi) {
+    case 1: launch_primal_t<QM, 1, E64>(g, t, count, CB, s); break;
+    case 8: launch_primal_t<QM, 8, E64>(g, t, count, CB, s); break;
+    case 16: launch_primal_t<QM, 16, E64>(g, t, count, CB, s); break;
+    case 32: launch_primal_t<QM, 32, E64>(g, t, count, CB, s); break;
+    default: launch_primal_t<QM, 64, E64>(g, t, count, CB, s); break;
+    }
+}
+
+static void launch_dual(pdg_ctx *ctx, uint32_t t)
+{
+    const Graph g = make_graph(ctx);
+    switch (ctx->QM) {
+    case 2: dual_q<2>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 3: dual_q<3>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 4: dual_q<4>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 5: dual_q<5>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 6: dual_q<6>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 7: dual_q<7>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    default: dual_q<8>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    }
+}
+
+template <bool E64>
+static void launch_primal_e(pdg_ctx *ctx, uint32_t t, int count)
+{
+    const Graph g = make_graph(ctx);
+    switch (ctx->QM) {
+    case 2: primal_q<2, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 3: primal_q<3, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 4: primal_q<4, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 5: primal_q<5, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 6: primal_q<6, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 7: primal_q<7, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    default: primal_q<8, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    }
+}
+
+static void launch_primal(pdg_ctx *ctx, uint32_t t, int count)
+{
+    if (ctx->cfg.precision == PDG_PRECISION_F64)
+        launch_primal_e<true>(ctx, t, count);
+    else
+        launch_primal_e<false>(ctx, t, count);
+}
+
+template <int QM>
+static void decompose_q(bool f64, int64_t m, const int32_t *qs, const int32_t *qd, const void *phi,
+                        const int32_t *dest, uint8_t *out, uint32_t *bad, hipStream_t s)
+{
+    if (f64)
+        k_decompose<QM, double><<<grid_for(m, 128), 128, 0, s>>>(
+            m, qs, qd, static_cast<const double *>(phi), dest, out, bad);
+    else
+        k_decompose<QM, float><<<grid_for(m, 128), 128, 0, s>>>(
+            m, qs, qd, static_cast<const float *>(phi), dest, out, bad);
+}
+
+static void launch_decompose(int qm, bool f64, int64_t m, const int32_t *qs, const int32_t *qd,
+                             const void *phi, const int32_t *dest, uint8_t *out, uint32_t *bad,
+                             hipStream_t s)
+{
+    switch (qm) {
+    case 2: decompose_q<2>(f64, m, qs, qd, phi, dest, out, bad, s); break;
+    case 3: decompose_q<3>(f64, m, qs, qd, phi, dest, out, bad, s); break;
+    case 4: decompose_q<4>(f64, m, qs, qd, phi, dest, out, bad, s); break;
+    case 5: decompose_q<5>(f64, m, qs, qd, phi, dest, out, bad, s); break;
+    case 6: decompose_q<6>(f64, m, qs, qd, phi, dest, out, bad, s); break;
+    case 7: decompose_q<7>(f64, m, qs, qd, phi, dest, out, bad, s); break;
+    default: decompose_q<8>(f64, m, qs, qd, phi, dest, out, bad, s); break;
+    }
+}
+
+// Finite-entry check of an edit batch before anything is changed.
+template <int QM, typename T>
+__global__ void k_check_tables(int64_t m, const int32_t *__restrict__ src,
+                               const int32_t *__restrict__ dst, const uint8_t *__restrict__ q,
+                               const T *__restrict__ phi, uint32_t *__restrict__ bad)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const int qs = q[src[k]], qd = q[dst[k]];
+    const T *L = phi + k * QM * QM;
+    for (int a = 0; a < qs; ++a)
+        for (int b = 0; b < qd; ++b)
+            if (!isfinite((double)L[a * QM + b])) atomicOr(bad, 1u);
+}
+
+template <int QM>
+static void check_q(bool f64, int64_t m, const int32_t *s, const int32_t *d, const uint8_t *q,
+                    const void *phi, uint32_t *bad, hipStream_t st)
+{
+    if (f64)
+        k_check_tables<QM, double><<<grid_for(m), 256, 0, st>>>(m, s, d, q,
+                                                               static_cast<const double *>(phi), bad);
+    else
+        k_check_tables<QM, float><<<grid_for(m), 256, 0, st>>>(m, s, d, q,
+                                                              static_cast<const float *>(phi), bad);
+}
+
+static void launch_check(int qm, bool f64, int64_t m, const int32_t *s, const int32_t *d,
+                         const uint8_t *q, const void *phi, uint32_t *bad, hipStream_t st)
+{
+    switch (qm) {
+    case 2: check_q<2>(f64, m, s, d, q, phi, bad, st); break;
+    case 3: check_q<3>(f64, m, s, d, q, phi, bad, st); break;
+    case 4: check_q<4>(f64, m, s, d, q, phi, bad, st); break;
+    case 5: check_q<5>(f64, m, s, d, q, phi, bad, st); break;
+    case 6: check_q<6>(f64, m, s, d, q, phi, bad, st); break;
+    case 7: check_q<7>(f64, m, s, d, q, phi, bad, st); break;
+    default: check_q<8>(f64, m, s, d, q, phi, bad, st); break;
+    }
+}
+
+// ---------------------------------------------------------------- edge store
+static uint32_t slack_for(uint32_t k) { return std::max<uint32_t>(2u, k / 4u); }
+
+struct Patches {
+    std::vector<uint32_t> idx, val;        // pool entries
+    std::vector<uint32_t> node, off, cnt;  // node segment headers
+    bool full = false;                     // whole pool and every header
+};
+
+// Lay every node's live entries out again, leaving room for `need` appends.
+static pdg_status full_compact(pdg_ctx *ctx, const std::vector<uint32_t> &need, Patches &P)
+{
+    Store &st = ctx->st;
+    const int64_t n = ctx->n;
+    std::vector<uint32_t> noff(n), ncap(n);
+    uint64_t total = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t want = st.nlive[i] + need[i];
+        ncap[i] = want ? want + slack_for(want) : 0;
+        noff[i] = (uint32_t)total;
+        total += ncap[i];
+    }
+    const uint64_t size = total + total / 4 + 1024;
+    if (size >= 0xFFFFFFF0ull) return fail(ctx, PDG_ECAPACITY, "incidence pool exceeds 2^32 entries");
+    std::vector<uint32_t> npool((size_t)size, kTomb);
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t w = 0;
+        for (uint32_t k = 0; k < st.cnt[i]; ++k) {
+            const uint32_t e = st.pool[st.off[i] + k];
+            if (e == kTomb) continue;
+            npool[noff[i] + w] = e;
+            const uint32_t slot = e >> 1;
+            if (e & 1u)
+                st.pos1[slot] = w;
+            else
+                st.pos0[slot] = w;
+            ++w;
+        }
+        st.off[i] = noff[i];
+        st.cnt[i] = w;
+        st.cap[i] = ncap[i];
+    }
+    st.pool.swap(npool);
+    st.pool_top = (int64_t)total;
+    P.full = true;
+    P.idx.clear();
+    P.val.clear();
+    return PDG_OK;
+}
+
+static void relocate(pdg_ctx *ctx, int64_t i, uint32_t need, Patches &P)
+{
+    Store &st = ctx->st;
+    const uint32_t want = st.nlive[i] + need;
+    const uint32_t ncap = want + slack_for(want);
+    const uint32_t noff = (uint32_t)st.pool_top;
+    st.pool_top += ncap;
+    uint32_t w = 0;
+    for (uint32_t k = 0; k < st.cnt[i]; ++k) {
+        const uint32_t e = st.pool[st.off[i] + k];
+        if (e == kTomb) continue;
+        st.pool[noff + w] = e;
+        if (!P.full) {
+            P.idx.push_back(noff + w);
+            P.val.push_back(e);
+        }
+        const uint32_t slot = e >> 1;
+        if (e & 1u)
+            st.pos1[slot] = w;
+        else
+            st.pos0[slot] = w;
+        ++w;
+    }
+    st.off[i] = noff;
+    st.cnt[i] = w;
+    st.cap[i] = ncap;
+}
+
+static void append(pdg_ctx *ctx, int64_t i, uint32_t e, Patches &P)
+{
+    Store &st = ctx->st;
+    const uint32_t p = st.cnt[i]++;
+    st.pool[st.off[i] + p] = e;
+    if (!P.full) {
+        P.idx.push_back(st.off[i] + p);
+        P.val.push_back(e);
+    }
+    const uint32_t slot = e >> 1;
+    if (e & 1u)
+        st.pos1[slot] = p;
+    else
+        st.pos0[slot] = p;
+    st.nlive[i]++;
+}
+
+// Push host-side changes of the incidence structure to the device.
+static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &touched)
+{
+    Store &st = ctx->st;
+    if (P.full) {
+        if ((int64_t)st.pool.size() > ctx->dev_pool_cap) {
+            PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            if (ctx->d_pool) PDG_HIP(ctx, hipFree(ctx->d_pool));
+            ctx->d_pool = nullptr;
+            ctx->dev_pool_cap = 0;
+            PDG_TRY(dalloc(ctx, (void **)&ctx->d_pool, (int64_t)st.pool.size() * 4));
+            ctx->dev_pool_cap = (int64_t)st.pool.size();
+        }
+        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_pool, st.pool.data(), st.pool.size() * 4,
+                                    hipMemcpyHostToDevice, ctx->stream));
+        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_off, st.off.data(), (size_t)ctx->n * 4,
+                                    hipMemcpyHostToDevice, ctx->stream));
+        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_cnt, st.cnt.data(), (size_t)ctx->n * 4,
+                                    hipMemcpyHostToDevice, ctx->stream));
+        PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        return PDG_OK;
+    }
+    if (st.pool_top > ctx->dev_pool_cap)
+        return fail(ctx, PDG_EINVAL, "internal: pool beyond device capacity without full upload");
+    const int64_t np = (int64_t)P.idx.size();
+    const int64_t nn = (int64_t)touched.size();
+    std::vector<uint32_t> hn(nn), ho(nn), hc(nn);
+    for (int64_t k = 0; k < nn; ++k) {
+        hn[k] = (uint32_t)touched[k];
+        ho[k] = st.off[touched[k]];
+        hc[k] = st.cnt[touched[k]];
+    }
+    void *s;
+    PDG_TRY(scratch(ctx, 4 * (2 * np + 3 * nn) + 64, &s));
+    uint32_t *di = (uint32_t *)s, *dv = di + np, *dn = dv + np, *dof = dn + nn, *dc = dof + nn;
+    if (np) {
+        PDG_HIP(ctx, hipMemcpyAsync(di, P.idx.data(), np * 4, hipMemcpyHostToDevice, ctx->stream));
+        PDG_HIP(ctx, hipMemcpyAsync(dv, P.val.data(), np * 4, hipMemcpyHostToDevice, ctx->stream));
+        k_scatter_u32<<<grid_for(np), 256, 0, ctx->stream>>>(np, di, dv, ctx->d_pool);
+        PDG_HIP(ctx, hipGetLastError());
+    }
+    if (nn) {
+        PDG_HIP(ctx, hipMemcpyAsync(dn, hn.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
+        PDG_HIP(ctx, hipMemcpyAsync(dof, ho.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
+        PDG_HIP(ctx, hipMemcpyAsync(dc, hc.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
+        k_scatter_nodes<<<grid_for(nn), 256, 0, ctx->stream>>>(nn, dn, dof, dc, ctx->d_off,
+                                                               ctx->d_cnt);
+        PDG_HIP(ctx, hipGetLastError());
+    }
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PDG_OK;
+}
+
+static void free_all(pdg_ctx *ctx)
+{
+    void *ps[] = {ctx->d_q,   ctx->d_lam,    ctx->d_x,   ctx->d_counts, ctx->d_src,
+                  ctx->d_dst, ctx->d_uid,    ctx->d_sq,  ctx->d_params, ctx->d_z,
+                  ctx->d_off, ctx->d_cnt,    ctx->d_pool, ctx->d_flag,  ctx->d_scratch};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+}
+
+}  // namespace pdg
+
+using namespace pdg;
+
+// ======================================================================= ABI
+extern "C" {
+
+const char *pdg_last_error(const pdg_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_global_err.c_str();
+}
+
+pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_ctx **out)
+{
+    if (!cfg || !out) return fail(nullptr, PDG_EINVAL, "null argument");
+    *out = nullptr;
+    if (cfg->n_chains < 1 || cfg->n_chains > (1 << 26))
+        return fail(nullptr, PDG_EINVAL, "n_chains must be in [1, 2^26]");
+    if (cfg->q_max < 2 || cfg->q_max > 8) return fail(nullptr, PDG_EINVAL, "q_max must be in [2, 8]");
+    if (cfg->node_capacity < 1 || cfg->edge_capacity < 1 || cfg->edge_capacity >= (1ll << 31))
+        return fail(nullptr, PDG_EINVAL, "capacities must be >= 1 (edges < 2^31)");
+    if (cfg->precision != PDG_PRECISION_F32 && cfg->precision != PDG_PRECISION_F64)
+        return fail(nullptr, PDG_EINVAL, "precision must be PDG_PRECISION_F32 or _F64");
+    if (cfg->reserved != 0 || cfg->burn_in < 0) return fail(nullptr, PDG_EINVAL, "bad config");
+    if ((int64_t)cfg->node_capacity * cfg->n_chains > (1ll << 40))
+        return fail(nullptr, PDG_ECAPACITY, "node_capacity * n_chains too large");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(nullptr, PDG_EINVAL, "no such HIP device");
+    pdg_ctx *ctx = new (std::nothrow) pdg_ctx();
+    if (!ctx) return fail(nullptr, PDG_ENOMEM, "host allocation failed");
+    ctx->cfg = *cfg;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)stream;
+    ctx->QM = cfg->q_max;
+    ctx->D = dim_d(ctx->QM);
+    ctx->C = cfg->n_chains;
+    ctx->LPI = choose_lpi(ctx->C);
+    ctx->CB = (int)cdiv(ctx->C, ctx->LPI);
+    ctx->Wz = ctx->C <= 32 ? 1 : 2 * (int)cdiv(ctx->C, 64);
+    ctx->bbytes = block_bytes(ctx->QM);
+    pdg_status s = PDG_OK;
+    auto bail = [&](pdg_status code) {
+        std::string m = ctx->err;
+        free_all(ctx);
+        delete ctx;
+        g_global_err = m;
+        return code;
+    };
+    if (hipSetDevice(device) != hipSuccess) return bail(fail(ctx, PDG_EHIP, "hipSetDevice failed"));
+    const int64_t N = cfg->node_capacity, S = cfg->edge_capacity;
+    if ((s = dalloc(ctx, (void **)&ctx->d_q, N)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_lam, N * ctx->QM * 8)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_x, N * ctx->C)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_counts, N * ctx->QM * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_src, S * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_dst, S * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_uid, S * 8)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_sq, S)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_params, S * ctx->bbytes)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_z, S * (int64_t)ctx->D * ctx->Wz * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_off, N * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_cnt, N * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_flag, 64)))
+        return bail(s);
+    if (hipMemsetAsync(ctx->d_uid, 0, S * 8, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_counts, 0, N * ctx->QM * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_x, 0, N * ctx->C, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return bail(fail(ctx, PDG_EHIP, "initial clear failed"));
+    Store &st = ctx->st;
+    try {
+        st.S = S;
+        st.uid.assign(S, 0);
+        st.gen.assign(S, 0);
+        st.src.assign(S, 0);
+        st.dst.assign(S, 0);
+        st.pos0.assign(S, 0);
+        st.pos1.assign(S, 0);
+        st.free_stack.resize(S);
+        for (int64_t j = 0; j < S; ++j) st.free_stack[j] = (int32_t)(S - 1 - j);
+    } catch (...) {
+        return bail(fail(ctx, PDG_ENOMEM, "host allocation failed"));
+    }
+    *out = ctx;
+    return PDG_OK;
+}
+
+pdg_status pdg_destroy(pdg_ctx *ctx)
+{
+    if (!ctx) return PDG_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+    return PDG_OK;
+}
+
+pdg_status pdg_set_nodes(pdg_ctx *ctx, int64_t n, const int32_t *d_q, const void *d_log_unary)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (ctx->nodes_set) return fail(ctx, PDG_ESTATE, "nodes already set");
+    if (n < 1 || n > ctx->cfg.node_capacity) return fail(ctx, PDG_EINVAL, "n out of range");
+    if (!d_q || !d_log_unary) return fail(ctx, PDG_EINVAL, "null pointer");
+    PDG_TRY(set_dev(ctx));
+    PDG_TRY(clear_flag(ctx));
+    if (ctx->cfg.precision == PDG_PRECISION_F64)
+        k_set_nodes<double><<<grid_for(n), 256, 0, ctx->stream>>>(
+            n, ctx->QM, d_q, static_cast<const double *>(d_log_unary), ctx->d_q, ctx->d_lam,
+            ctx->d_flag);
+    else
+        k_set_nodes<float><<<grid_for(n), 256, 0, ctx->stream>>>(
+            n, ctx->QM, d_q, static_cast<const float *>(d_log_unary), ctx->d_q, ctx->d_lam,
+            ctx->d_flag);
+    PDG_HIP(ctx, hipGetLastError());
+    uint32_t bad = 0;
+    PDG_TRY(read_flag(ctx, &bad));
+    if (bad & 2u) return fail(ctx, PDG_EINVAL, "q_i outside [2, q_max]");
+    if (bad & 1u) return fail(ctx, PDG_ENONPOS, "non-finite log unary");
+    Store &st = ctx->st;
+    st.off.assign(n, 0);
+    st.cnt.assign(n, 0);
+    st.cap.assign(n, 0);
+    st.nlive.assign(n, 0);
+    ctx->n = n;
+    PDG_HIP(ctx, hipMemsetAsync(ctx->d_off, 0, n * 4, ctx->stream));
+    PDG_HIP(ctx, hipMemsetAsync(ctx->d_cnt, 0, n * 4, ctx->stream));
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->nodes_set = true;
+    return PDG_OK;
+}
+
+pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const int32_t *d_dst,
+                            const void *d_log_phi, uint64_t *d_uid_out)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (!ctx->nodes_set) return fail(ctx, PDG_ESTATE, "pdg_set_nodes first");
+    if (ctx->phase != 0) return fail(ctx, PDG_ESTATE, "edits only between sweeps");
+    if (m < 0) return fail(ctx, PDG_EINVAL, "m < 0");
+    if (m == 0) return PDG_OK;
+    if (!d_src || !d_dst || !d_log_phi) return fail(ctx, PDG_EINVAL, "null pointer");
+    PDG_TRY(set_dev(ctx));
+    Store &st = ctx->st;
+    if ((int64_t)st.free_stack.size() < m) return fail(ctx, PDG_ECAPACITY, "edge capacity exhausted");
+    std::vector<int32_t> hs(m), hd(m);
+    PDG_HIP(ctx, hipMemcpyAsync(hs.data(), d_src, m * 4, hipMemcpyDeviceToHost, ctx->stream));
+    PDG_HIP(ctx, hipMemcpyAsync(hd.data(), d_dst, m * 4, hipMemcpyDeviceToHost, ctx->stream));
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t k = 0; k < m; ++k) {
+        if (hs[k] < 0 || hs[k] >= ctx->n || hd[k] < 0 || hd[k] >= ctx->n)
+            return fail(ctx, PDG_EINVAL, "edge endpoint out of range");
+        if (hs[k] == hd[k]) return fail(ctx, PDG_EINVAL, "self-loop is not a pairwise factor");
+    }
+    for (int64_t k = 0; k < m; ++k)
+        if (st.gen[st.free_stack[st.free_stack.size() - 1 - k]] == 0xFFFFFFFFu)
+            return fail(ctx, PDG_ECAPACITY, "uid space of a slot exhausted");
+    // tables must be finite before anything changes
+    PDG_TRY(clear_flag(ctx));
+    launch_check(ctx->QM, ctx->cfg.precision == PDG_PRECISION_F64, m, d_src, d_dst, ctx->d_q,
+                 d_log_phi, ctx->d_flag, ctx->stream);
+    PDG_HIP(ctx, hipGetLastError());
+    uint32_t bad = 0;
+    PDG_TRY(read_flag(ctx, &bad));
+    if (bad) return fail(ctx, PDG_ENONPOS, "non-finite log factor entry");
+
+    // slots and uids
+    std::vector<int32_t> slots(m);
+    std::vector<uint64_t> uids(m);
+    for (int64_t k = 0; k < m; ++k) {
+        const int32_t s = st.free_stack.back();
+        st.free_stack.pop_back();
+        st.gen[s] += 1;
+        const uint64_t u = ((uint64_t)st.gen[s] << 32) | (uint32_t)s;
+        slots[k] = s;
+        uids[k] = u;
+        st.uid[s] = u;
+        st.src[s] = hs[k];
+        st.dst[s] = hd[k];
+        st.hwm = std::max<int64_t>(st.hwm, (int64_t)s + 1);
+    }
+    st.live += m;
+    // incidence: room first (relocation or full compaction), then appends in batch order
+    Patches P;
+    std::vector<uint32_t> need;
+    std::vector<int64_t> touched;
+    try {
+        need.assign(ctx->n, 0);
+        for (int64_t k = 0; k < m; ++k) {
+            if (need[hs[k]]++ == 0) touched.push_back(hs[k]);
+            if (need[hd[k]]++ == 0) touched.push_back(hd[k]);
+        }
+    } catch (...) {
+        return fail(ctx, PDG_ENOMEM, "host allocation failed");
+    }
+    uint64_t room = 0;
+    for (int64_t i : touched)
+        if (st.cnt[i] + need[i] > st.cap[i]) {
+            const uint32_t want = st.nlive[i] + need[i];
+            room += want + slack_for(want);
+        }
+    if ((uint64_t)st.pool_top + room > (uint64_t)st.pool.size()) {
+        PDG_TRY(full_compact(ctx, need, P));
+    } else {
+        for (int64_t i : touched)
+            if (st.cnt[i] + need[i] > st.cap[i]) relocate(ctx, i, need[i], P);
+    }
+    for (int64_t k = 0; k < m; ++k) {
+        append(ctx, hs[k], ((uint32_t)slots[k] << 1) | 0u, P);
+        append(ctx, hd[k], ((uint32_t)slots[k] << 1) | 1u, P);
+    }
+    // device: slot arrays, decomposition, incidence
+    void *s;
+    PDG_TRY(scratch(ctx, 8 * m + 4 * m * 3 + 64, &s));
+    uint64_t *du = (uint64_t *)s;
+    int32_t *dslot = (int32_t *)(du + m), *dqs = dslot + m, *dqd = dqs + m;
+    PDG_HIP(ctx, hipMemcpyAsync(du, uids.data(), m * 8, hipMemcpyHostToDevice, ctx->stream));
+    PDG_HIP(ctx, hipMemcpyAsync(dslot, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
+    k_slot_write<<<grid_for(m), 256, 0, ctx->stream>>>(m, dslot, d_src, d_dst, du, ctx->d_q,
+                                                       ctx->d_src, ctx->d_dst, ctx->d_uid,
+                                                       ctx->d_sq, dqs, dqd, d_uid_out);
+    PDG_HIP(ctx, hipGetLastError());
+    PDG_TRY(clear_flag(ctx));
+    launch_decompose(ctx->QM, ctx->cfg.precision == PDG_PRECISION_F64, m, dqs, dqd, d_log_phi,
+                     dslot, ctx->d_params, ctx->d_flag, ctx->stream);
+    PDG_HIP(ctx, hipGetLastError());
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    PDG_TRY(upload(ctx, P, touched));
+    return PDG_OK;
+}
+
+pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (ctx->phase != 0) return fail(ctx, PDG_ESTATE, "edits only between sweeps");
+    if (m < 0) return fail(ctx, PDG_EINVAL, "m < 0");
+    if (m == 0) return PDG_OK;
+    if (!d_uid) return fail(ctx, PDG_EINVAL, "null pointer");
+    PDG_TRY(set_dev(ctx));
+    Store &st = ctx->st;
+    std::vector<uint64_t> hu(m);
+    PDG_HIP(ctx, hipMemcpyAsync(hu.data(), d_uid, m * 8, hipMemcpyDeviceToHost, ctx->stream));
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<int32_t> slots(m);
+    for (int64_t k = 0; k < m; ++k) {
+        const uint64_t u = hu[k];
+        const int64_t s = (int64_t)(u & 0xFFFFFFFFull);
+        if (u == 0 || s >= st.S || st.uid[s] != u) {
+            for (int64_t j = 0; j < k; ++j) st.uid[slots[j]] = hu[j];
+            return fail(ctx, PDG_ENOTFOUND, "uid " + std::to_string(u) + " is not a live edge");
+        }
+        slots[k] = (int32_t)s;
+        st.uid[s] = 0;  // also catches a uid repeated within the batch
+    }
+    Patches P;
+    std::vector<int64_t> touched;
+    for (int64_t k = 0; k < m; ++k) {
+        const int32_t s = slots[k];
+        const int32_t a = st.src[s], b = st.dst[s];
+        const uint32_t ia = st.off[a] + st.pos0[s], ib = st.off[b] + st.pos1[s];
+        st.pool[ia] = kTomb;
+        st.pool[ib] = kTomb;
+        P.idx.push_back(ia);
+        P.val.push_back(kTomb);
+        P.idx.push_back(ib);
+        P.val.push_back(kTomb);
+        st.nlive[a]--;
+        st.nlive[b]--;
+        st.free_stack.push_back(s);
+    }
+    st.live -= m;
+    void *sp;
+    PDG_TRY(scratch(ctx, 4 * m + 64, &sp));
+    PDG_HIP(ctx, hipMemcpyAsync(sp, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
+    k_slot_clear<<<grid_for(m), 256, 0, ctx->stream>>>(m, (const int32_t *)sp, ctx->d_uid);
+    PDG_HIP(ctx, hipGetLastError());
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    PDG_TRY(upload(ctx, P, touched));
+    return PDG_OK;
+}
+
+pdg_status pdg_num_edges(pdg_ctx *ctx, int64_t *h_live)
+{
+    if (!ctx || !h_live) return fail(ctx, PDG_EINVAL, "null argument");
+    *h_live = ctx->st.live;
+    return PDG_OK;
+}
+
+pdg_status pdg_live_uids(pdg_ctx *ctx, uint64_t *d_uid_out)
+{
+    if (!ctx || !d_uid_out) return fail(ctx, PDG_EINVAL, "null argument");
+    PDG_TRY(set_dev(ctx));
+    std::vector<uint64_t> out;
+    out.reserve(ctx->st.live);
+    for (int64_t s = 0; s < ctx->st.hwm; ++s)
+        if (ctx->st.uid[s]) out.push_back(ctx->st.uid[s]);
+    if (!out.empty()) {
+        PDG_HIP(ctx, hipMemcpyAsync(d_uid_out, out.data(), out.size() * 8, hipMemcpyHostToDevice,
+                                    ctx->stream));
+        PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return PDG_OK;
+}
+
+pdg_status pdg_params_layout(int32_t q_max, int64_t *h_bytes, int64_t *h_off_thr, int64_t *h_off_v,
+                             int64_t *h_off_c)
+{
+    if (q_max < 2 || q_max > 8) return fail(nullptr, PDG_EINVAL, "q_max must be in [2, 8]");
+    const int64_t D = dim_d(q_max);
+    if (h_bytes) *h_bytes = block_bytes(q_max);
+    if (h_off_thr) *h_off_thr = 0;
+    if (h_off_v) *h_off_v = 8 * D;
+    if (h_off_c) *h_off_c = 16 * D;
+    return PDG_OK;
+}
+
+pdg_status pdg_decompose(int64_t m, int32_t q_max, const int32_t *d_qs, const int32_t *d_qd,
+                         const void *d_log_phi, int32_t precision, void *d_params_out, void *stream)
+{
+    if (q_max < 2 || q_max > 8) return fail(nullptr, PDG_EINVAL, "q_max must be in [2, 8]");
+    if (m < 0) return fail(nullptr, PDG_EINVAL, "m < 0");
+    if (m == 0) return PDG_OK;
+    if (!d_qs || !d_qd || !d_log_phi || !d_params_out) return fail(nullptr, PDG_EINVAL, "null pointer");
+    if (precision != PDG_PRECISION_F32 && precision != PDG_PRECISION_F64)
+        return fail(nullptr, PDG_EINVAL, "bad precision");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *bad = nullptr;
+    if (hipMalloc((void **)&bad, 4) != hipSuccess) return fail(nullptr, PDG_ENOMEM, "hipMalloc failed");
+    k_fill_u32<<<1, 64, 0, s>>>(bad, 1, 0u);
+    launch_decompose(q_max, precision == PDG_PRECISION_F64, m, d_qs, d_qd, d_log_phi, nullptr,
+                     (uint8_t *)d_params_out, bad, s);
+    uint32_t hb = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return fail(nullptr, PDG_EHIP, std::string("decompose: ") + hipGetErrorString(e));
+    if (hb & 2u) return fail(nullptr, PDG_EINVAL, "a state count is outside [2, q_max]");
+    if (hb) return fail(nullptr, PDG_ENONPOS, "non-finite log factor entry");
+    return PDG_OK;
+}
+
+pdg_status pdg_init_chains(pdg_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (!ctx->nodes_set) return fail(ctx, PDG_ESTATE, "pdg_set_nodes first");
+    PDG_TRY(set_dev(ctx));
+    const int64_t nc = ctx->n * ctx->C;
+    k_init<<<grid_for(nc), 256, 0, ctx->stream>>>(ctx->n, ctx->C, ctx->d_q, ctx->d_x,
+                                                  (uint32_t)ctx->cfg.seed,
+                                                  (uint32_t)(ctx->cfg.seed >> 32));
+    PDG_HIP(ctx, hipGetLastError());
+    ctx->t = 0;
+    ctx->phase = 0;
+    return PDG_OK;
+}
+
+pdg_status pdg_set_state(pdg_ctx *ctx, const uint8_t *d_x)
+{
+    if (!ctx || !d_x) return fail(ctx, PDG_EINVAL, "null argument");
+    if (!ctx->nodes_set) return fail(ctx, PDG_ESTATE, "pdg_set_nodes first");
+    PDG_TRY(set_dev(ctx));
+    PDG_HIP(ctx, hipMemcpyAsync(ctx->d_x, d_x, ctx->n * ctx->C, hipMemcpyDeviceToDevice, ctx->stream));
+    return PDG_OK;
+}
+
+pdg_status pdg_get_state(pdg_ctx *ctx, uint8_t *d_x_out)
+{
+    if (!ctx || !d_x_out) return fail(ctx, PDG_EINVAL, "null argument");
+    PDG_TRY(set_dev(ctx));
+    PDG_HIP(ctx, hipMemcpyAsync(d_x_out, ctx->d_x, ctx->n * ctx->C, hipMemcpyDeviceToDevice, ctx->stream));
+    return PDG_OK;
+}
+
+pdg_status pdg_get_sweep(pdg_ctx *ctx, int64_t *h_t)
+{
+    if (!ctx || !h_t) return fail(ctx, PDG_EINVAL, "null argument");
+    *h_t = ctx->t;
+    return PDG_OK;
+}
+
+pdg_status pdg_set_sweep(pdg_ctx *ctx, int64_t t)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (t < 0 || t >= 0xFFFFFFFFll) return fail(ctx, PDG_EINVAL, "sweep counter out of range");
+    if (ctx->phase != 0) return fail(ctx, PDG_ESTATE, "between sweeps only");
+    ctx->t = t;
+    return PDG_OK;
+}
+
+pdg_status pdg_dual_phase(pdg_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (!ctx->nodes_set) return fail(ctx, PDG_ESTATE, "pdg_set_nodes first");
+    if (ctx->phase != 0) return fail(ctx, PDG_ESTATE, "primal phase pending");
+    if (ctx->t + 1 >= 0xFFFFFFFFll) return fail(ctx, PDG_ECAPACITY, "sweep counter exhausted");
+    PDG_TRY(set_dev(ctx));
+    ctx->t += 1;
+    if (ctx->st.hwm > 0) {
+        launch_dual(ctx, (uint32_t)ctx->t);
+        PDG_HIP(ctx, hipGetLastError());
+    }
+    ctx->phase = 1;
+    return PDG_OK;
+}
+
+pdg_status pdg_primal_phase(pdg_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (ctx->phase != 1) return fail(ctx, PDG_ESTATE, "dual phase first");
+    const int count = ctx->t > ctx->cfg.burn_in ? 1 : 0;
+    if (count && (uint64_t)(ctx->counted + 1) * (uint64_t)ctx->C > 0xFFFFFFFFull)
+        return fail(ctx, PDG_ECAPACITY, "marginal counters would overflow; read and reset them");
+    PDG_TRY(set_dev(ctx));
+    launch_primal(ctx, (uint32_t)ctx->t, count);
+    PDG_HIP(ctx, hipGetLastError());
+    ctx->counted += count;
+    ctx->phase = 0;
+    return PDG_OK;
+}
+
+pdg_status pdg_sweep(pdg_ctx *ctx, int64_t n_sweeps)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (n_sweeps < 0) return fail(ctx, PDG_EINVAL, "n_sweeps < 0");
+    for (int64_t k = 0; k < n_sweeps; ++k) {
+        PDG_TRY(pdg_dual_phase(ctx));
+        PDG_TRY(pdg_primal_phase(ctx));
+    }
+    return PDG_OK;
+}
+
+pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_t *d_theta_out)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (m < 0) return fail(ctx, PDG_EINVAL, "m < 0");
+    if (m == 0) return PDG_OK;
+    if (!d_uid || !d_theta_out) return fail(ctx, PDG_EINVAL, "null pointer");
+    PDG_TRY(set_dev(ctx));
+    std::vector<uint64_t> hu(m);
+    PDG_HIP(ctx, hipMemcpyAsync(hu.data(), d_uid, m * 8, hipMemcpyDeviceToHost, ctx->stream));
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<int32_t> slots(m);
+    for (int64_t k = 0; k < m; ++k) {
+        const int64_t s = (int64_t)(hu[k] & 0xFFFFFFFFull);
+        if (hu[k] == 0 || s >= ctx->st.S || ctx->st.uid[s] != hu[k])
+            return fail(ctx, PDG_ENOTFOUND, "uid is not a live edge");
+        slots[k] = (int32_t)s;
+    }
+    void *sp;
+    PDG_TRY(scratch(ctx, 4 * m + 64, &sp));
+    PDG_HIP(ctx, hipMemcpyAsync(sp, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
+    k_get_duals<<<grid_for(m * ctx->C), 256, 0, ctx->stream>>>(m, ctx->C, ctx->D, ctx->Wz,
+                                                               (const int32_t *)sp, ctx->d_z,
+                                                               d_theta_out);
+    PDG_HIP(ctx, hipGetLastError());
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PDG_OK;
+}
+
+pdg_status pdg_get_marginals(pdg_ctx *ctx, double *d_out, int64_t *h_samples)
+{
+    if (!ctx || !d_out) return fail(ctx, PDG_EINVAL, "null argument");
+    PDG_TRY(set_dev(ctx));
+    const int64_t samples = ctx->counted * ctx->C;
+    const double inv = samples ? 1.0 / (double)samples : 0.0;
+    const int64_t nq = ctx->n * ctx->QM;
+    k_marginals<<<grid_for(nq), 256, 0, ctx->stream>>>(nq, ctx->d_counts, inv, d_out);
+    PDG_HIP(ctx, hipGetLastError());
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (h_samples) *h_samples = samples;
+    return PDG_OK;
+}
+
+pdg_status pdg_get_counts(pdg_ctx *ctx, uint32_t *d_out, int64_t *h_samples)
+{
+    if (!ctx || !d_out) return fail(ctx, PDG_EINVAL, "null argument");
+    PDG_TRY(set_dev(ctx));
+    PDG_HIP(ctx, hipMemcpyAsync(d_out, ctx->d_counts, ctx->n * ctx->QM * 4, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (h_samples) *h_samples = ctx->counted * ctx->C;
+    return PDG_OK;
+}
+
+pdg_status pdg_reset_marginals(pdg_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    PDG_TRY(set_dev(ctx));
+    const int64_t nq = ctx->n * ctx->QM;
+    k_fill_u32<<<grid_for(nq), 256, 0, ctx->stream>>>(ctx->d_counts, nq, 0u);
+    PDG_HIP(ctx, hipGetLastError());
+    ctx->counted = 0;
+    return PDG_OK;
+}
+
+pdg_status pdg_sync(pdg_ctx *ctx)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    PDG_TRY(set_dev(ctx));
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    PDG_HIP(ctx, hipGetLastError());
+    return PDG_OK;
+}
+
+}  // extern "C"

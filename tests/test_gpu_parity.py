@@ -1,0 +1,370 @@
+"""GPU path vs the FP64 oracle, through the C ABI (``-m gpu``).
+
+Parity bar (the sampler's floating point decides integers):
+  * init and every *unflagged* draw bit-exact; a draw is flagged when its
+    uniform lies within 1e-6 of a CDF boundary computed by the oracle in FP64;
+  * flagged draws may differ and must be fewer than 1e-5 of all draws;
+  * FP64 contexts (FP64 exp in the node draw) match free-running trajectories
+    and marginal counters exactly;
+  * marginals agree with enumeration within 3 batch-means standard errors.
+Teacher forcing: both sides start a sweep from the same x; the oracle's primal
+phase is fed the GPU's duals, so one flagged dual cannot cascade.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_1611_06684_amd import workloads as W
+from tests import brute
+
+pytestmark = pytest.mark.gpu
+
+FLAG_BUDGET = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _sampler(model, C, seed, **kw):
+    from paper_1611_06684_amd.pdg import Sampler
+    return Sampler(model, C, seed=seed, **kw)
+
+
+def _random_state(model, C, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.random((model.n, C)) * model.q[:, None]).astype(np.uint8)
+
+
+def _u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def teacher_forced(s, model, dec, seed, x_in, t):
+    """One sweep t on GPU and oracle from x_in.  Returns a dict of counts."""
+    import torch
+    s.t = t - 1
+    s.set_state(torch.as_tensor(x_in, device=s.dev))
+    s.dual_phase()
+    th_g = _u64(s.duals(s.uids))
+    s.primal_phase()
+    x_g = s.state().cpu().numpy()
+    uid = _u64(s.uids)
+    th_o, dflag, _, _ = oracle.sweep(model, dec, uid, seed, t, x_in)
+    x_o, pflag = oracle.primal_phase(model, dec, seed, t, th_g)
+    dmis = th_g ^ th_o
+    bad_dual = int(np.count_nonzero(dmis & ~dflag))
+    xmis = x_g != x_o
+    bad_x = int(np.count_nonzero(xmis & (pflag == 0)))
+    D = (model.q[model.src] - 1) * (model.q[model.dst] - 1)
+    n_draws = int(D.sum()) * x_in.shape[1] + model.n * x_in.shape[1]
+    n_flag = int(sum(bin(int(v)).count("1") for v in dflag.ravel() if v)) + int(pflag.sum())
+    return dict(bad_dual=bad_dual, bad_x=bad_x, dual_mis=int(np.count_nonzero(dmis)),
+                x_mis=int(xmis.sum()), flagged=n_flag, draws=n_draws)
+
+
+def _models():
+    yield "tiny_ising_4x4_f64_C1", W.ising_grid(4, 4, seed=0), 1
+    yield "grid_37x29_q4_f32_C64", W.table_grid(37, 29, 4, seed=1), 64
+    yield "grid_20x23_q3_f32_C32", W.table_grid(20, 23, 3, seed=2, pair_std=0.6), 32
+    yield "random_mixed_q235_f32_C5", W.random_graph(300, 900, [2, 3, 5], seed=3, dtype="f32"), 5
+    yield "random_mixed_q2to7_f64_C17", W.random_graph(200, 500, [2, 4, 7], seed=4), 17
+    yield "grid_16x16_q2_f32_C100", W.table_grid(16, 16, 2, seed=5, pair_std=1.0), 100
+    yield "ising_10x10_f64_C13", W.ising_grid(10, 10, seed=6, J_half_range=0.8), 13
+    yield "chung_lu_4096_q8_f32_C32", W.chung_lu(4096, 8, seed=7), 32
+
+
+@pytest.mark.parametrize("name,model,C", list(_models()), ids=[m[0] for m in _models()])
+def test_teacher_forced_sweeps(name, model, C):
+    _say(f"[teacher-forced] {name} n={model.n} m={model.m} C={C}")
+    seed = 11
+    s = _sampler(model, C, seed)
+    dec = oracle.decompose(model)
+    tot = dict(flagged=0, draws=0)
+    for k, t in enumerate((1, 2, 7, 123457)):
+        x_in = _random_state(model, C, 100 + k)
+        r = teacher_forced(s, model, dec, seed, x_in, t)
+        _say(f"  t={t} {r}")
+        assert r["bad_dual"] == 0, r
+        assert r["bad_x"] == 0, r
+        tot["flagged"] += r["flagged"]
+        tot["draws"] += r["draws"]
+    s.close()
+    assert tot["flagged"] <= max(FLAG_BUDGET * tot["draws"], 3), tot
+
+
+def test_init_is_bit_exact():
+    for model, C, seed in [(W.random_graph(500, 10, [2, 3, 5, 8], seed=1), 37, 5),
+                           (W.ising_grid(4, 4), 1, 0), (W.table_grid(30, 30, 4), 64, 2**40 + 3)]:
+        s = _sampler(model, C, seed)
+        s.init()
+        x_g = s.state().cpu().numpy()
+        x_o = oracle.init_state(model, C, seed)
+        assert (x_g == x_o).all()
+        assert s.t == 0
+        s.close()
+
+
+def test_decompose_matches_oracle_conditionals():
+    """pdg_decompose (the kernel the insert path runs) against the oracle's
+    Theorem parameters: dual thresholds T(y,y') = ceil(p(theta=0|y,y') 2^24 - 1/2)
+    and primal fields (all-zero duals, and the per-dual increment beta)."""
+    import torch
+    from paper_1611_06684_amd import pdg
+    rng = np.random.default_rng(9)
+    for qm, f64 in [(2, True), (3, False), (4, False), (5, True), (8, False)]:
+        m = 3000
+        qs = rng.integers(2, qm + 1, size=m).astype(np.int32)
+        qd = rng.integers(2, qm + 1, size=m).astype(np.int32)
+        dt = np.float64 if f64 else np.float32
+        Lam = rng.normal(0, 1.5, size=(m, qm, qm)).astype(dt)
+        Lam[:5] *= 8.0  # large odds ratios
+        Lam[5:10] *= 1e-7  # near-unit odds ratios
+        dev = torch.device("cuda", 0)
+        bb, o_thr, o_v, o_c = pdg.pdg_params_layout(qm)
+        out = torch.zeros(m * bb, dtype=torch.uint8, device=dev)
+        tq = [torch.as_tensor(a, device=dev) for a in (qs, qd, Lam)]
+        pdg.pdg_decompose(m, qm, tq[0].data_ptr(), tq[1].data_ptr(), tq[2].data_ptr(),
+                          1 if f64 else 0, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        blk = out.cpu().numpy().reshape(m, bb)
+        D = (qm - 1) ** 2
+        thr = blk[:, o_thr:o_thr + 8 * D].copy().view(np.uint64)
+        v = blk[:, o_v:o_v + 8 * D].copy().view(np.float64)
+        c = blk[:, o_c:o_c + 16 * (qm - 1)].copy().view(np.float64).reshape(m, 2, qm - 1)
+        q = np.zeros(2 * m, np.int32)
+        q[0::2], q[1::2] = qs, qd
+        model = W.Model(q, np.zeros((2 * m, qm)), np.arange(0, 2 * m, 2, dtype=np.int32),
+                        np.arange(1, 2 * m, 2, dtype=np.int32), Lam.astype(np.float64))
+        dec = oracle.decompose(model)
+        n_exact = n_edge = 0
+        for e in range(m):
+            for a in range(1, qs[e]):
+                row_o = dec.rrow[e, a] + sum(dec.par[e, (a - 1) * (qd[e] - 1) + b - 1, 0]
+                                             for b in range(1, qd[e]))
+                row_g = c[e, 0, a - 1] + sum(v[e, (a - 1) * (qd[e] - 1) + b - 1]
+                                            for b in range(1, qd[e]))
+                assert abs(row_o - row_g) < 1e-9 * (1 + abs(row_o)), (e, a, row_o, row_g)
+                for b in range(1, qd[e]):
+                    d = (a - 1) * (qd[e] - 1) + (b - 1)
+                    par = dec.par[e, d]
+                    tscale = 1e-9 * (1 + abs(par[3]))
+                    assert abs(-2 * v[e, d] - par[3]) < tscale
+                    assert abs(2 * abs(v[e, d]) - par[4]) < 1e-9 * (1 + abs(par[4]))
+                    neg = bool(int(thr[e, d]) >> 63)
+                    tp = int(thr[e, d]) & 0x1FFFFFF
+                    tm = (int(thr[e, d]) >> 32) & 0x1FFFFFF
+                    for y in (0, 1):
+                        for yp in (0, 1):
+                            s1 = (1 - 2 * y) * (-1 if neg else 1)
+                            s2 = 1 - 2 * yp
+                            T = tp if (s1 > 0 and s2 > 0) else (tm if (s1 < 0 and s2 < 0) else 1 << 23)
+                            p0 = 1.0 - oracle.dual_p1(par, y, yp)
+                            exact = np.ceil(p0 * 2**24 - 0.5)
+                            if T == exact:
+                                n_exact += 1
+                            else:
+                                n_edge += 1
+                                frac = p0 * 2**24 - 0.5
+                                assert abs(frac - np.round(frac)) < 1e-6, (e, d, y, yp, T, exact)
+            for b in range(1, qd[e]):
+                col_o = dec.rcol[e, b] + sum(dec.par[e, (a - 1) * (qd[e] - 1) + b - 1, 1]
+                                             for a in range(1, qs[e]))
+                col_g = c[e, 1, b - 1] - sum(abs(v[e, (a - 1) * (qd[e] - 1) + b - 1])
+                                            for a in range(1, qs[e]))
+                assert abs(col_o - col_g) < 1e-9 * (1 + abs(col_o)), (e, b, col_o, col_g)
+        _say(f"  q_max={qm}: thresholds exact {n_exact}, on an integer boundary {n_edge}")
+
+
+def test_decompose_rejects_nonfinite():
+    import torch
+    from paper_1611_06684_amd import pdg
+    dev = torch.device("cuda", 0)
+    Lam = torch.zeros((2, 3, 3), dtype=torch.float32, device=dev)
+    Lam[1, 2, 1] = float("inf")
+    q = torch.full((2,), 3, dtype=torch.int32, device=dev)
+    out = torch.zeros(2 * pdg.pdg_params_layout(3)[0], dtype=torch.uint8, device=dev)
+    with pytest.raises(pdg.PdgError) as e:
+        pdg.pdg_decompose(2, 3, q.data_ptr(), q.data_ptr(), Lam.data_ptr(), 0, out.data_ptr(),
+                          torch.cuda.current_stream().cuda_stream)
+    assert e.value.code == pdg.PDG_ENONPOS
+
+
+def test_fp64_free_running_trajectory_and_counts_exact():
+    """FP64 context: 2000 free-running sweeps from init, final state and
+    marginal counters identical to the oracle's."""
+    model = W.ising_grid(6, 5, seed=3, J_half_range=0.7)
+    for C in (1, 8, 64):
+        s = _sampler(model, C, seed=21, burn_in=100)
+        s.init()
+        s.sweep(2000)
+        x_g = s.state().cpu().numpy()
+        import torch
+        cnt_g = torch.zeros((model.n, model.q_max), dtype=torch.int32, device=s.dev)
+        from paper_1611_06684_amd import pdg
+        pdg.pdg_get_counts(s.ctx, cnt_g.data_ptr())
+        cnt_g = cnt_g.cpu().numpy().astype(np.uint64)
+        dec = oracle.decompose(model)
+        x_o = oracle.init_state(model, C, 21)
+        cnt_o, nf, nd = oracle.run(model, dec, _u64(s.uids), 21, x_o, 0, 2000, burn_in=100)
+        assert (x_g == x_o).all(), C
+        assert (cnt_g == cnt_o).all(), C
+        s.close()
+
+
+def test_tiny_marginals_vs_enumeration():
+    """Tiny plain workload on the GPU: 4x4 binary grid, FP64, 1 chain, 1e5
+    sweeps, seed 0; within 3 batch-means SE of enumeration."""
+    import torch
+    from paper_1611_06684_amd import pdg
+    model = W.ising_grid(4, 4, seed=0)
+    exact = brute.exact_marginals(model)
+    s = _sampler(model, 1, seed=0)
+    s.init()
+    s.sweep(10000)
+    est = []
+    cnt = torch.zeros((model.n, 2), dtype=torch.int32, device=s.dev)
+    for b in range(50):
+        s.reset_marginals()
+        s.sweep(1800)
+        n = pdg.pdg_get_counts(s.ctx, cnt.data_ptr())
+        est.append(cnt.cpu().numpy() / n)
+    mean, se = brute.batch_means(np.array(est))
+    z = np.abs(mean[:, 1] - exact[:, 1]) / se[:, 1]
+    _say("  z:", np.round(z, 2))
+    assert (z < 3).all(), z
+    s.close()
+
+
+def test_edits_then_teacher_forced():
+    """Churn on a Chung-Lu graph: remove / insert batches between sweeps; after
+    each batch the GPU sweep matches the oracle on the live edge set (by uid)."""
+    import torch
+    model = W.chung_lu(2048, 5, seed=12)
+    C = 32
+    seed = 5
+    s = _sampler(model, C, seed, edge_capacity=model.m + 2000)
+    churn = W.Churn(model.n, 5, model.meta["weights"], seed=13, frac=0.05)
+    live_src, live_dst, live_Lam = model.src.copy(), model.dst.copy(), model.Lam.copy()
+    live_uid = _u64(s.uids).copy()
+    s.init()
+    s.sweep(3)
+    for rnd in range(4):
+        rem, ns, nd, nL = churn.next_batch(live_uid)
+        s.remove_edges(torch.as_tensor(rem.view(np.int64), device=s.dev))
+        new_uid = _u64(s.insert_edges(ns, nd, nL))
+        keep = ~np.isin(live_uid, rem)
+        live_uid = np.concatenate([live_uid[keep], new_uid])
+        live_src = np.concatenate([live_src[keep], ns])
+        live_dst = np.concatenate([live_dst[keep], nd])
+        live_Lam = np.concatenate([live_Lam[keep], nL])
+        cur = W.Model(model.q, model.lam, live_src, live_dst, live_Lam)
+        assert sorted(_u64(s.live_uids()).tolist()) == sorted(live_uid.tolist())
+        s.uids = torch.as_tensor(live_uid.view(np.int64), device=s.dev)
+        dec = oracle.decompose(cur)
+        x_in = _random_state(cur, C, 50 + rnd)
+        r = teacher_forced(s, cur, dec, seed, x_in, 10 + rnd)
+        _say(f"  round {rnd}: live={len(live_uid)} {r}")
+        assert r["bad_dual"] == 0 and r["bad_x"] == 0, r
+        s.sweep(2)
+    # uids are never reused
+    assert len(set(live_uid.tolist())) == len(live_uid)
+    s.close()
+
+
+def test_error_paths():
+    import torch
+    from paper_1611_06684_amd import pdg
+    model = W.random_graph(50, 60, [3], seed=2, dtype="f32")
+    s = _sampler(model, 4, 0, edge_capacity=62)
+    dev = s.dev
+    with pytest.raises(pdg.PdgError) as e:
+        s.remove_edges(torch.tensor([12345], dtype=torch.int64, device=dev))
+    assert e.value.code == pdg.PDG_ENOTFOUND
+    u0 = s.uids[:1]
+    with pytest.raises(pdg.PdgError) as e:  # repeated uid: nothing removed
+        s.remove_edges(torch.cat([u0, u0]))
+    assert e.value.code == pdg.PDG_ENOTFOUND
+    assert pdg.pdg_num_edges(s.ctx) == 60
+    with pytest.raises(pdg.PdgError) as e:
+        s.insert_edges([1], [1], np.zeros((1, 3, 3), np.float32))
+    assert e.value.code == pdg.PDG_EINVAL
+    with pytest.raises(pdg.PdgError) as e:
+        s.insert_edges([1], [99], np.zeros((1, 3, 3), np.float32))
+    assert e.value.code == pdg.PDG_EINVAL
+    bad = np.zeros((1, 3, 3), np.float32)
+    bad[0, 1, 1] = np.nan
+    with pytest.raises(pdg.PdgError) as e:
+        s.insert_edges([1], [2], bad)
+    assert e.value.code == pdg.PDG_ENONPOS
+    with pytest.raises(pdg.PdgError) as e:
+        s.insert_edges([1, 2, 3], [2, 3, 4], np.zeros((3, 3, 3), np.float32))
+    assert e.value.code == pdg.PDG_ECAPACITY
+    assert pdg.pdg_num_edges(s.ctx) == 60
+    s.dual_phase()
+    with pytest.raises(pdg.PdgError) as e:
+        s.insert_edges([1], [2], np.zeros((1, 3, 3), np.float32))
+    assert e.value.code == pdg.PDG_ESTATE
+    with pytest.raises(pdg.PdgError) as e:
+        s.dual_phase()
+    assert e.value.code == pdg.PDG_ESTATE
+    s.primal_phase()
+    s.sync()
+    s.close()
+
+
+def test_full_size_plain_grid_sampled():
+    """Plain grid workload at full size (1024x1024, q=4, FP32 tables, 64 chains),
+    in the launch configuration the benchmark times: one sweep from init, then
+    sampled nodes and their incident edges checked one by one by the oracle."""
+    import torch
+    model = W.table_grid(1024, 1024, 4, seed=0)
+    C, seed = 64, 0
+    _say(f"[full-size] n={model.n} m={model.m}")
+    s = _sampler(model, C, seed)
+    s.init()
+    s.sweep(3)
+    x_prev = s.state().cpu().numpy()
+    s.dual_phase()
+    uids = _u64(s.uids)
+    rng = np.random.default_rng(0)
+    nodes = rng.choice(model.n, size=300, replace=False)
+    # incident edges of the sampled nodes (grid: src/dst lookup)
+    order = np.argsort(np.concatenate([model.src, model.dst]), kind="stable")
+    ends = np.concatenate([model.src, model.dst])[order]
+    lo, hi = np.searchsorted(ends, nodes), np.searchsorted(ends, nodes, side="right")
+    inc = {int(i): order[a:b] for i, a, b in zip(nodes, lo, hi)}
+    edges = np.unique(np.concatenate(list(inc.values())) % model.m)
+    th_g = _u64(s.duals(torch.as_tensor(uids[edges].view(np.int64), device=s.dev)))
+    s.primal_phase()
+    x_new = s.state().cpu().numpy()
+    t = s.t
+    subm = model.subset_edges(edges)
+    dec = oracle.decompose(subm)
+    sub = {int(e): k for k, e in enumerate(edges)}
+    n_draw = n_flag = 0
+    for k, e in enumerate(edges):
+        for c in range(C):
+            th, fl = oracle.dual_edge(subm, dec, k,
+                                      x_prev[model.src[e], c], x_prev[model.dst[e], c],
+                                      uids[e], c, t, seed)
+            assert ((int(th_g[k, c]) ^ th) & ~fl) == 0, (e, c)
+            n_draw += 9
+            n_flag += bin(fl).count("1")
+    for i in nodes:
+        es = inc[int(i)]
+        sides = (es >= model.m).astype(np.int32)
+        rows = np.array([sub[int(e % model.m)] for e in es])
+        for c in range(C):
+            xo, fo = oracle.primal_node(subm, dec, int(i), rows, sides,
+                                        [th_g[r, c] for r in rows], c, t, seed)
+            assert fo or xo == x_new[i, c], (i, c)
+            n_draw += 1
+            n_flag += fo
+    _say(f"  sampled draws {n_draw}, flagged {n_flag}")
+    assert n_flag <= max(FLAG_BUDGET * n_draw, 3)
+    s.close()

@@ -21,8 +21,10 @@ MUTANTS = {
     "no_row_swap": ("if (p11 * p22 - p12 * p21 < 0.0) {", "if (0) {"),
     "swap_not_undone": ("if (swapped) {", "if (0 && swapped) {"),
     "scaling_transposed": ("double s11 = p11 / p12;", "double s11 = p11 / p21;"),
-    "remark_sign": ("double sphi = 0.5 * (sqrt(1.0 + a) - sqrt(1.0 - a));",
-                    "double sphi = 0.5 * (sqrt(1.0 + a) - sqrt(1.0 - a * a));"),
+    "remark_sign": ("double sphi = a / (sqrt(1.0 + a) + sqrt(1.0 - a));",
+                    "double sphi = a / (sqrt(1.0 + a) - sqrt(1.0 - a));"),
+    "remark_cos": ("double cphi = 0.5 * (sqrt(1.0 + a) + sqrt(1.0 - a));",
+                   "double cphi = 0.5 * (sqrt(1.0 + a) + sqrt(1.0 - a * a));"),
     "theorem_alpha_from_C": ("par[0] = log(B21 / B11);", "par[0] = log(C21 / C11);"),
     "theorem_beta_sign": ("par[3] = log((B22 * B11) / (B12 * B21));",
                           "par[3] = -log((B22 * B11) / (B12 * B21));"),
