@@ -30,12 +30,11 @@ sys.path.insert(0, ROOT)
 # ---- VALU roofline of the dual kernel ---------------------------------------
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 full-rate 32-bit VALU
 # lane-operations per second.  Algorithmic work of one dual draw, in full-rate
-# issue slots: one fifth of a Philox4x32-10 call (10 rounds, each two 32x32->64
-# multiplies at MAD64_SLOTS slots and four 32-bit xors) plus the three-way
-# threshold select and the compare (3 slots).
+# issue slots: one fifth of a Philox4x32-10 call -- 10 rounds, each two 32x32->64
+# multiplies (v_mad_u64_u32, measured full rate on gfx950) and two three-input
+# xors (v_bitop3_b32) -- plus three compares that decide the draw (11 slots).
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-MAD64_SLOTS = 4
-PHILOX_SLOTS = 10 * (2 * MAD64_SLOTS + 4)
+PHILOX_SLOTS = 10 * (2 + 2)
 DRAW_SLOTS = PHILOX_SLOTS / 5.0 + 3.0
 
 
