@@ -101,17 +101,21 @@ pdg_status pdg_live_uids(pdg_ctx *ctx, uint64_t *d_uid_out);
 pdg_status pdg_decompose(int64_t m, int32_t q_max, const int32_t *d_qs, const int32_t *d_qd,
                          const void *d_log_phi, int32_t precision, void *d_params_out,
                          void *stream);
-/* Bytes per edge of the parameter block and the offsets (in bytes, within a
- * block) of its three arrays, for q_max:
- *   thr  uint64 [(q_max-1)^2]: bits 0-24 T+, bits 32-56 T-, bit 63 = 1 if the
- *        entry's log odds-ratio is negative.  The dual draw of entry (a,b) is
- *        1 iff U >= T(k), U the 24-bit integer of the draw, k = s1 + s2 with
- *        s1 = sign-adjusted (1 - 2[x_src = a]), s2 = 1 - 2[x_dst = b];
- *        T(+2) = T+, T(-2) = T-, T(0) = 2^23.
- *   v    double [(q_max-1)^2]: sigma_ab * t_ab, t = log tan(phi) <= 0.
- *   c    double [2][q_max-1]: src-side and dst-side constant field per state >= 1. */
-pdg_status pdg_params_layout(int32_t q_max, int64_t *h_bytes_per_edge, int64_t *h_off_thr,
-                             int64_t *h_off_v, int64_t *h_off_c);
+/* Bytes per edge of the parameter block and the byte offsets of its parts,
+ * for q_max (D = (q_max-1)^2, entry d = (a-1)(q_dst-1) + (b-1)):
+ *   sign  uint64: bit d set when entry d's log odds ratio is negative (the
+ *         row swap of the negative-determinant case, Sec. 4.1).
+ *   thr   uint32 [D][2]: T+ * 256 - 1 and T- * 256, where T(k) =
+ *         ceil(p(theta = 0) 2^24 - 1/2) for the dual logit t k, k in {+2, -2}
+ *         (k = 0 gives T = 2^23).  The draw with 24-bit integer U is theta = 1
+ *         iff U >= T(k), k = sigma (1 - 2[x_src = a]) + (1 - 2[x_dst = b]).
+ *   h     double [D]: half the field increment of src state a when
+ *         theta_ab = 1 (2h is the Theorem's beta1); dst state b gets 2|h| (beta2).
+ *   c0    double [2][q_max-1]: field of each state >= 1 when every dual of the
+ *         edge is 0 (the Theorem's alpha terms plus the table's first row /
+ *         column), src side then dst side. */
+pdg_status pdg_params_layout(int32_t q_max, int64_t *h_bytes_per_edge, int64_t *h_off_sign,
+                             int64_t *h_off_thr, int64_t *h_off_h, int64_t *h_off_c0);
 
 /* x(0) = floor(u q_i) for every node and chain (generator phase INIT);
  * resets the sweep counter to 0. */

@@ -331,10 +331,13 @@ static int orc_categorical(int32_t qn, const double *L, double u, int *flag)
     return x;
 }
 
+/* The node draw's uniform: call (node quad = node / 4, sub = chain c, sweep t),
+ * word node mod 4. */
 static int orc_primal_draw(int32_t qn, const double *L, int64_t node, int32_t c, uint32_t t,
                            uint64_t seed, int *flag)
 {
-    double u = orc_uniform(seed, ORC_PHASE_PRIMAL, (uint64_t)node, (uint32_t)(c / 4), t, c % 4);
+    double u = orc_uniform(seed, ORC_PHASE_PRIMAL, (uint64_t)(node / 4), (uint32_t)c, t,
+                           (int)(node % 4));
     return orc_categorical(qn, L, u, flag);
 }
 

@@ -47,6 +47,7 @@ struct pdg_ctx {
     int64_t bbytes = 0;
     int64_t n = 0;
     bool nodes_set = false;
+    bool uq = false;  // every node has q_max states
     int64_t t = 0;
     int phase = 0;  // 0: between sweeps, 1: dual done
     int64_t counted = 0;
@@ -175,88 +176,101 @@ static Graph make_graph(pdg_ctx *ctx)
     g.n = ctx->n;
     g.hwm = ctx->st.hwm;
     g.C = ctx->C;
-    g.Wz = ctx->Wz;
+    g.CB = (int32_t)cdiv(ctx->C, 64);
     g.k0 = (uint32_t)ctx->cfg.seed;
     g.k1 = (uint32_t)(ctx->cfg.seed >> 32);
     return g;
 }
 
 // ------------------------------------------------------------- kernel dispatch
-template <int QM, int LPI>
+template <int QM, int LPI, bool UQ>
 static void launch_dual_t(const Graph &g, uint32_t t, int CB, hipStream_t s)
 {
     constexpr int P = 64 / LPI;
     const int64_t waves = cdiv(g.hwm, P) * CB;
-    k_dual<QM, LPI><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+    k_dual<QM, LPI, UQ><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
 }
 
-template <int QM, int LPI, bool E64>
+template <int QM, int LPI, bool UQ, bool E64>
 static void launch_primal_t(const Graph &g, uint32_t t, int count, int CB, hipStream_t s)
 {
     constexpr int P = 64 / LPI;
-    const int64_t waves = cdiv(g.n, P) * CB;
-    k_primal<QM, LPI, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
+    const int64_t waves = cdiv(cdiv(g.n, 4), P) * CB;
+    k_primal<QM, LPI, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
 }
 
-template <int QM>
+template <int QM, bool UQ>
 static void dual_q(int lpi, const Graph &g, uint32_t t, int CB, hipStream_t s)
 {
     switch (lpi) {
-    case 1: launch_dual_t<QM, 1>(g, t, CB, s); break;
-    case 8: launch_dual_t<QM, 8>(g, t, CB, s); break;
-    case 16: launch_dual_t<QM, 16>(g, t, CB, s); break;
-    case 32: launch_dual_t<QM, 32>(g, t, CB, s); break;
-    default: launch_dual_t<QM, 64>(g, t, CB, s); break;
+    case 1: launch_dual_t<QM, 1, UQ>(g, t, CB, s); break;
+    case 8: launch_dual_t<QM, 8, UQ>(g, t, CB, s); break;
+    case 16: launch_dual_t<QM, 16, UQ>(g, t, CB, s); break;
+    case 32: launch_dual_t<QM, 32, UQ>(g, t, CB, s); break;
+    default: launch_dual_t<QM, 64, UQ>(g, t, CB, s); break;
     }
 }
 
-template <int QM, bool E64>
+template <int QM, bool UQ, bool E64>
 static void primal_q(int lpi, const Graph &g, uint32_t t, int count, int CB, hipStream_t s)
 {
     switch (lpi) {
-    case 1: launch_primal_t<QM, 1, E64>(g, t, count, CB, s); break;
-    case 8: launch_primal_t<QM, 8, E64>(g, t, count, CB, s); break;
-    case 16: launch_primal_t<QM, 16, E64>(g, t, count, CB, s); break;
-    case 32: launch_primal_t<QM, 32, E64>(g, t, count, CB, s); break;
-    default: launch_primal_t<QM, 64, E64>(g, t, count, CB, s); break;
+    case 1: launch_primal_t<QM, 1, UQ, E64>(g, t, count, CB, s); break;
+    case 8: launch_primal_t<QM, 8, UQ, E64>(g, t, count, CB, s); break;
+    case 16: launch_primal_t<QM, 16, UQ, E64>(g, t, count, CB, s); break;
+    case 32: launch_primal_t<QM, 32, UQ, E64>(g, t, count, CB, s); break;
+    default: launch_primal_t<QM, 64, UQ, E64>(g, t, count, CB, s); break;
+    }
+}
+
+template <bool UQ>
+static void launch_dual_u(pdg_ctx *ctx, uint32_t t)
+{
+    const Graph g = make_graph(ctx);
+    switch (ctx->QM) {
+    case 2: dual_q<2, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 3: dual_q<3, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 4: dual_q<4, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 5: dual_q<5, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 6: dual_q<6, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 7: dual_q<7, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    default: dual_q<8, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
     }
 }
 
 static void launch_dual(pdg_ctx *ctx, uint32_t t)
 {
-    const Graph g = make_graph(ctx);
-    switch (ctx->QM) {
-    case 2: dual_q<2>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 3: dual_q<3>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 4: dual_q<4>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 5: dual_q<5>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 6: dual_q<6>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 7: dual_q<7>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    default: dual_q<8>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    }
+    if (ctx->uq)
+        launch_dual_u<true>(ctx, t);
+    else
+        launch_dual_u<false>(ctx, t);
 }
 
-template <bool E64>
+template <bool UQ, bool E64>
 static void launch_primal_e(pdg_ctx *ctx, uint32_t t, int count)
 {
     const Graph g = make_graph(ctx);
     switch (ctx->QM) {
-    case 2: primal_q<2, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
-    case 3: primal_q<3, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
-    case 4: primal_q<4, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
-    case 5: primal_q<5, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
-    case 6: primal_q<6, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
-    case 7: primal_q<7, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
-    default: primal_q<8, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 2: primal_q<2, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 3: primal_q<3, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 4: primal_q<4, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 5: primal_q<5, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 6: primal_q<6, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    case 7: primal_q<7, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    default: primal_q<8, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
     }
 }
 
 static void launch_primal(pdg_ctx *ctx, uint32_t t, int count)
 {
-    if (ctx->cfg.precision == PDG_PRECISION_F64)
-        launch_primal_e<true>(ctx, t, count);
-    else
-        launch_primal_e<false>(ctx, t, count);
+    const bool e64 = ctx->cfg.precision == PDG_PRECISION_F64;
+    if (ctx->uq) {
+        if (e64) launch_primal_e<true, true>(ctx, t, count);
+        else launch_primal_e<true, false>(ctx, t, count);
+    } else {
+        if (e64) launch_primal_e<false, true>(ctx, t, count);
+        else launch_primal_e<false, false>(ctx, t, count);
+    }
 }
 
 template <int QM>
@@ -603,6 +617,12 @@ pdg_status pdg_set_nodes(pdg_ctx *ctx, int64_t n, const int32_t *d_q, const void
     PDG_TRY(read_flag(ctx, &bad));
     if (bad & 2u) return fail(ctx, PDG_EINVAL, "q_i outside [2, q_max]");
     if (bad & 1u) return fail(ctx, PDG_ENONPOS, "non-finite log unary");
+    {
+        std::vector<int32_t> hq(n);
+        PDG_HIP(ctx, hipMemcpyAsync(hq.data(), d_q, n * 4, hipMemcpyDeviceToHost, ctx->stream));
+        PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->uq = std::all_of(hq.begin(), hq.end(), [&](int32_t v) { return v == ctx->QM; });
+    }
     Store &st = ctx->st;
     st.off.assign(n, 0);
     st.cnt.assign(n, 0);
@@ -787,15 +807,15 @@ pdg_status pdg_live_uids(pdg_ctx *ctx, uint64_t *d_uid_out)
     return PDG_OK;
 }
 
-pdg_status pdg_params_layout(int32_t q_max, int64_t *h_bytes, int64_t *h_off_thr, int64_t *h_off_v,
-                             int64_t *h_off_c)
+pdg_status pdg_params_layout(int32_t q_max, int64_t *h_bytes, int64_t *h_off_sign,
+                             int64_t *h_off_thr, int64_t *h_off_h, int64_t *h_off_c0)
 {
     if (q_max < 2 || q_max > 8) return fail(nullptr, PDG_EINVAL, "q_max must be in [2, 8]");
-    const int64_t D = dim_d(q_max);
     if (h_bytes) *h_bytes = block_bytes(q_max);
-    if (h_off_thr) *h_off_thr = 0;
-    if (h_off_v) *h_off_v = 8 * D;
-    if (h_off_c) *h_off_c = 16 * D;
+    if (h_off_sign) *h_off_sign = 0;
+    if (h_off_thr) *h_off_thr = off_thr(q_max);
+    if (h_off_h) *h_off_h = off_h(q_max);
+    if (h_off_c0) *h_off_c0 = off_c0(q_max);
     return PDG_OK;
 }
 
@@ -935,9 +955,8 @@ pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_
     void *sp;
     PDG_TRY(scratch(ctx, 4 * m + 64, &sp));
     PDG_HIP(ctx, hipMemcpyAsync(sp, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
-    k_get_duals<<<grid_for(m * ctx->C), 256, 0, ctx->stream>>>(m, ctx->C, ctx->D, ctx->Wz,
-                                                               (const int32_t *)sp, ctx->d_z,
-                                                               d_theta_out);
+    k_get_duals<<<grid_for(m * ctx->C), 256, 0, ctx->stream>>>(m, ctx->D, make_graph(ctx),
+                                                               (const int32_t *)sp, d_theta_out);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PDG_OK;

@@ -1,24 +1,32 @@
 // HIP kernels of the primal-dual Gibbs sweep for gfx950 (wave64).
 //
-// Work mapping.  A wave covers P = 64 / LPI items (edges in the dual phase,
-// nodes in the primal phase) times LPI chains; lane = (item, chain).  With 64
-// or more chains (LPI = 64) an item owns whole waves, so everything per item
-// (endpoints, parameter block, incidence segment) is wave-uniform and comes
-// through scalar loads; only x, the dual bits and the draws are per lane.
+// Work mapping.  A wave covers P = 64 / LPI items times LPI chains; lane =
+// (item, chain).  Items are edges in the dual phase and node quads (four
+// consecutive nodes) in the primal phase.  With 33 or more chains (LPI = 64)
+// an item owns whole waves, so everything per item -- endpoints, parameter
+// block, incidence segment, dual bit-plane words -- is wave-uniform and comes
+// through scalar loads, and a plane word is directly the lane mask of its
+// chains.
 //
 // Storage (device, all written by this library):
 //   x       uint8  [n][C]                 node states, chain fastest
 //   params  block  [slot]                 per-edge decomposition (layout below)
-//   z       uint32 [slot][D][Wz]          dual bit-planes: bit (c mod 32) of
-//                                         word c / 32 is theta of chain c
+//   z       [slot][chain block][D] words  dual bit-planes: with C <= 32 one
+//                                         32-bit word per (slot, d), bit c; with
+//                                         C > 32 one 64-bit word per (slot,
+//                                         block of 64 chains, d), bit c mod 64
 //   inc     uint32 pool                   per-node incidence segments
 //                                         [off, off + cnt): slot << 1 | side
 //                                         (side 0: node is src), or kTomb
 //   counts  uint32 [n][QM]                marginal counters
-// Parameter block of an edge (QM = q_max, D = (QM-1)^2):
-//   thr  uint64 [D]      dual thresholds (see k_decompose)
-//   v    double [D]      sigma * t per entry
-//   c    double [2][QM-1] constant field per state >= 1, src side then dst side
+// Parameter block of an edge (QM = q_max, D = (QM-1)^2, entry d = (a-1)(q_dst-1)+(b-1)):
+//   sign  uint64          bit d set when the entry's log odds ratio is negative
+//   thr   uint32 [D][2]   T+ * 256 - 1 and T- * 256 (thresholds on a 32-bit word
+//                         whose top 24 bits are the draw's integer U)
+//   h     double [D]      half the field increment of the src node's state a
+//                         when theta = 1 (the dst node's state b gets 2|h|)
+//   c0    double [2][QM-1] field of each state >= 1 when every dual of the
+//                         edge is 0, src side then dst side
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,9 +40,12 @@ namespace pdg {
 constexpr uint32_t kTomb = 0xFFFFFFFFu;
 
 __host__ __device__ constexpr int dim_d(int qm) { return (qm - 1) * (qm - 1); }
+__host__ __device__ constexpr int64_t off_thr(int) { return 8; }
+__host__ __device__ constexpr int64_t off_h(int qm) { return 8 + 8 * (int64_t)dim_d(qm); }
+__host__ __device__ constexpr int64_t off_c0(int qm) { return 8 + 16 * (int64_t)dim_d(qm); }
 __host__ __device__ constexpr int64_t block_bytes(int qm)
 {
-    return 16 * (int64_t)dim_d(qm) + 16 * (int64_t)(qm - 1);
+    return 8 + 16 * (int64_t)dim_d(qm) + 16 * (int64_t)(qm - 1);
 }
 
 struct Graph {
@@ -45,7 +56,7 @@ struct Graph {
     const uint64_t *__restrict__ uid;     // [slots], 0 = free slot
     const uint8_t *__restrict__ sq;       // [slots] q_src | q_dst << 4
     const uint8_t *__restrict__ params;   // [slots] parameter blocks
-    uint32_t *__restrict__ z;             // [slots][D][Wz]
+    uint32_t *__restrict__ z;             // dual bit-planes (layout above)
     const uint32_t *__restrict__ inc_off; // [n]
     const uint32_t *__restrict__ inc_cnt; // [n]
     const uint32_t *__restrict__ inc;     // pool
@@ -54,9 +65,16 @@ struct Graph {
     int64_t n;
     int64_t hwm;                          // slots [0, hwm) may be live
     int32_t C;
-    int32_t Wz;
+    int32_t CB;                           // blocks of 64 chains (1 when C <= 64)
     uint32_t k0, k1;                      // generator key
 };
+
+// u32 index of the plane word holding chain c of entry d of slot s.
+__device__ __forceinline__ uint64_t zword_index(const Graph &g, int64_t s, int d, int c, int D)
+{
+    if (g.C <= 32) return (uint64_t)s * D + d;
+    return (((uint64_t)s * g.CB + (c >> 6)) * D + d) * 2 + ((c >> 5) & 1);
+}
 
 // ---------------------------------------------------------------------------
 // a1: decomposition of one edge table (Sec. 4.1 + 4.2, closed form).
@@ -68,12 +86,14 @@ struct Graph {
 // a form that stays finite for any finite ell.  sigma = sign(ell) records the
 // row swap of the negative-determinant case.  The dual conditional is
 // logistic(t k) with k = sigma(1 - 2y) + (1 - 2y') in {-2, 0, 2}, so
-// p(theta = 0) = 1 / (1 + e^(t k)) takes three values and the draw compares
-// the 24-bit integer U of its uniform u = (U + 0.5) 2^-24 against
-// T = ceil(p0 2^24 - 0.5): theta = 0 iff U < T.  T(0) = 2^23.
-// Field of the one-hot bit: src side 1/2 ell + sigma t (1 - 2 theta),
-// dst side 1/2 ell + t (1 - 2 theta); the 1/2 ell and the rescaling unaries
-// L(a,0) - L(0,0), L(0,b) - L(0,0) are summed into c.
+// p(theta = 0) = 1 / (1 + e^(t k)) takes three values and a draw compares the
+// 24-bit integer U of its uniform u = (U + 0.5) 2^-24 with
+// T = ceil(p0 2^24 - 0.5): theta = 0 iff U < T; T(0) = 2^23, T+ = T(2) >= 2^23,
+// T- = T(-2) <= 2^23.
+// Field of the one-hot bit of the src state a: 1/2 ell + sigma t (1 - 2 theta)
+// = (1/2 ell + sigma t) + 2 theta h with h = -sigma t; of the dst state b:
+// (1/2 ell + t) + 2 theta |h|.  The theta-free parts and the rescaling unaries
+// L(a,0) - L(0,0), L(0,b) - L(0,0) are summed into c0.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double log_tan_phi(double ell)
 {
@@ -91,7 +111,8 @@ __device__ __forceinline__ uint32_t threshold24(double p0)
 
 // One thread per edge.  Reads table k (layout [m][QM][QM], type T) with node
 // states qs[k], qd[k]; writes the parameter block to out + dest[k] (dest may
-// be null: identity).  Sets *bad = 1 if a used entry is not finite.
+// be null: identity).  *bad |= 1 if a used entry is not finite, |= 2 if a
+// state count is outside [2, QM].
 template <int QM, typename T>
 __global__ void k_decompose(int64_t m, const int32_t *__restrict__ qs_arr,
                             const int32_t *__restrict__ qd_arr, const T *__restrict__ phi,
@@ -108,9 +129,9 @@ __global__ void k_decompose(int64_t m, const int32_t *__restrict__ qs_arr,
     }
     const T *L = phi + k * QM * QM;
     uint8_t *blk = out + (dest ? (int64_t)dest[k] : k) * block_bytes(QM);
-    uint64_t *thr = reinterpret_cast<uint64_t *>(blk);
-    double *v = reinterpret_cast<double *>(blk + 8 * D);
-    double *c = reinterpret_cast<double *>(blk + 16 * D);
+    uint32_t *thr = reinterpret_cast<uint32_t *>(blk + off_thr(QM));
+    double *h = reinterpret_cast<double *>(blk + off_h(QM));
+    double *c0 = reinterpret_cast<double *>(blk + off_c0(QM));
     int finite = 1;
     for (int a = 0; a < qs; ++a)
         for (int b = 0; b < qd; ++b) finite &= isfinite((double)L[a * QM + b]) ? 1 : 0;
@@ -124,9 +145,11 @@ __global__ void k_decompose(int64_t m, const int32_t *__restrict__ qs_arr,
     for (int a = 1; a < qs; ++a) crow[a] = (double)L[a * QM] - L00;
     for (int b = 1; b < qd; ++b) ccol[b] = (double)L[b] - L00;
     for (int d = 0; d < D; ++d) {
-        thr[d] = 0;
-        v[d] = 0.0;
+        thr[2 * d] = 0xFFFFFFFFu;
+        thr[2 * d + 1] = 0u;
+        h[d] = 0.0;
     }
+    uint64_t sign = 0;
     for (int a = 1; a < qs; ++a) {
         for (int b = 1; b < qd; ++b) {
             const double ell = (double)L[a * QM + b] + L00 - (double)L[a * QM] - (double)L[b];
@@ -135,20 +158,25 @@ __global__ void k_decompose(int64_t m, const int32_t *__restrict__ qs_arr,
             const uint32_t tp = threshold24(1.0 / (1.0 + exp(2.0 * t)));
             const uint32_t tm = threshold24(1.0 / (1.0 + exp(-2.0 * t)));
             const int d = (a - 1) * (qd - 1) + (b - 1);
-            thr[d] = (uint64_t)tp | ((uint64_t)tm << 32) | ((uint64_t)(neg ? 1 : 0) << 63);
-            v[d] = neg ? -t : t;
-            crow[a] += 0.5 * ell;
-            ccol[b] += 0.5 * ell;
+            thr[2 * d] = (uint32_t)((uint64_t)tp * 256u - 1u);
+            thr[2 * d + 1] = tm * 256u;
+            const double st = neg ? -t : t;
+            h[d] = -st;
+            crow[a] += 0.5 * ell + st;
+            ccol[b] += 0.5 * ell + t;
+            if (neg) sign |= 1ull << d;
         }
     }
+    *reinterpret_cast<uint64_t *>(blk) = sign;
     for (int a = 1; a < QM; ++a) {
-        c[a - 1] = crow[a];
-        c[(QM - 1) + a - 1] = ccol[a];
+        c0[a - 1] = crow[a];
+        c0[(QM - 1) + a - 1] = ccol[a];
     }
 }
 
 // ---------------------------------------------------------------------------
-// a2: x(0) = floor(u q) = floor((2U + 1) q / 2^25), U from phase INIT.
+// a2: x(0) = floor(u q) = floor((2U + 1) q / 2^25), U from phase INIT,
+// call (node, c / 4), word c mod 4.
 // ---------------------------------------------------------------------------
 __global__ void k_init(int64_t n, int32_t C, const uint8_t *__restrict__ q,
                        uint8_t *__restrict__ x, uint32_t k0, uint32_t k1)
@@ -167,69 +195,126 @@ __global__ void k_init(int64_t n, int32_t C, const uint8_t *__restrict__ q,
 template <int LPI>
 struct LaneMap {
     int lane;      // 0..63
-    int64_t item;  // edge slot or node
+    int64_t item;  // edge slot or node quad of this lane
+    int64_t base;  // item of lane 0 of the wave
     int c;         // chain
     int cb;        // chain block (LPI chains)
     __device__ __forceinline__ LaneMap(int32_t C)
     {
         constexpr int P = 64 / LPI;
         lane = threadIdx.x & 63;
-        const int64_t wave =
-            (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                             __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int CB = (C + LPI - 1) / LPI;
-        const int64_t group = wave / CB;
+        const int64_t group = (CB == 1) ? wave : wave / CB;
         cb = (int)(wave - group * CB);
-        item = group * P + (P == 1 ? 0 : lane / LPI);
+        base = group * P;
+        item = base + (P == 1 ? 0 : lane / LPI);
         c = cb * LPI + (LPI == 64 ? lane : lane % LPI);
     }
 };
 
+// v_writelane_b32: set lane `lane` (uniform) of `old` to the uniform `value`.
+extern "C" __device__ uint32_t pdg_writelane_i32(uint32_t value, uint32_t lane, uint32_t old)
+    __asm("llvm.amdgcn.writelane.i32");
+
+// Wave-uniform lane mask -> per-lane predicate without VALU work.
+__device__ __forceinline__ bool lane_bit(uint64_t mask)
+{
+    return __builtin_amdgcn_inverse_ballot_w64(mask);
+}
+
 // ---------------------------------------------------------------------------
 // a3: dual phase.  Every live edge, chain and entry d = (a-1)(q_dst-1)+(b-1):
-// theta = [U >= T(k)], U from call sub = 16 c + d / 5, value d mod 5.
-// The bits leave the wave as ballots, one 32-bit plane word per 32 chains.
+// theta = [U >= T(k)], U from call (uid, DUAL, 16 c + d / 5, t), value d mod 5.
+// The five values of a call are kept in "W form" (U in the top 24 bits of a
+// 32-bit word), so the three candidate thresholds are single compares:
+// U >= T+  <=>  W > T+ 256 - 1,  U >= 2^23  <=>  W >= 2^31,  U >= T-  <=>  W >= T- 256.
+// The compare results are lane masks; the (y, y', sigma) case analysis is mask
+// logic, and the ballot of theta is the dual bit-plane word.
+// UQ: every node has q_max states (compile-time entry loops).
 // ---------------------------------------------------------------------------
-template <int QM, int LPI>
+template <int QM, int LPI, bool UQ>
 __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
 {
     constexpr int D = dim_d(QM);
     constexpr int NCALL = (D + 4) / 5;
+    constexpr int NW = (LPI >= 32) ? 2 * D : 1;      // plane words gathered per wave
+    constexpr int NREG = (NW + 63) / 64;
     const LaneMap<LPI> lm(g.C);
     const int64_t slot = lm.item;
     const bool in_range = slot < g.hwm;
-    uint64_t uid = 0;
-    if (in_range) uid = g.uid[slot];
+    const int64_t sl = in_range ? slot : 0;
+    const uint64_t uid = in_range ? g.uid[sl] : 0ull;
     const bool live = uid != 0;
     const bool active = live && lm.c < g.C;
-    uint64_t zbits = 0;
+    int qs = QM, qd = QM;
+    if (!UQ && live) {
+        const uint32_t sq = g.sq[sl];
+        qs = (int)(sq & 15u);
+        qd = (int)(sq >> 4);
+    }
+    int xs = -1, xd = -1;
     if (active) {
-        const int32_t s = g.src[slot], d = g.dst[slot];
-        const uint32_t sq = g.sq[slot];
-        const int qs = (int)(sq & 15u), qd = (int)(sq >> 4);
-        const int xs = g.x[(int64_t)s * g.C + lm.c];
-        const int xd = g.x[(int64_t)d * g.C + lm.c];
-        const uint64_t *thr = reinterpret_cast<const uint64_t *>(g.params + slot * block_bytes(QM));
-        const int De = (qs - 1) * (qd - 1);
-        const uint32_t ulo = (uint32_t)uid, uhi = (uint32_t)(uid >> 32);
-        int a = 1, b = 1;
+        xs = g.x[(int64_t)g.src[sl] * g.C + lm.c];
+        xd = g.x[(int64_t)g.dst[sl] * g.C + lm.c];
+    }
+    const uint8_t *blk = g.params + sl * block_bytes(QM);
+    const uint64_t sign = *reinterpret_cast<const uint64_t *>(blk);
+    const uint32_t *thr = reinterpret_cast<const uint32_t *>(blk + off_thr(QM));
+    const int De = UQ ? D : (qs - 1) * (qd - 1);
+    const uint32_t ulo = (uint32_t)uid, uhi = (uint32_t)(uid >> 32);
+    const uint64_t mact = __ballot(active);
+    // lane masks of the one-hot bits y = [x_src = a], y' = [x_dst = b]
+    uint64_t mya[QM], myb[QM];
 #pragma unroll
-        for (int k = 0; k < NCALL; ++k) {
-            if (5 * k >= De) break;
-            const Words w = philox4x32_10(ulo, uhi, (kPhaseDual << 30) | (uint32_t)(16 * lm.c + k), t,
-                                          g.k0, g.k1);
-            const uint32_t U[5] = {w.w0 >> 8, w.w1 >> 8, w.w2 >> 8, w.w3 >> 8, fifth_u24(w)};
+    for (int v = 1; v < QM; ++v) {
+        mya[v] = UQ ? __ballot(xs == v) : 0ull;
+        myb[v] = UQ ? __ballot(xd == v) : 0ull;
+    }
+    uint32_t outr[NREG];
 #pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const int dd = 5 * k + j;
-                if (dd >= De) break;
-                const uint64_t th = thr[dd];
-                const uint32_t tp = (uint32_t)th & 0x1FFFFFFu;
-                const uint32_t tm = (uint32_t)(th >> 32) & 0x1FFFFFFu;
-                const bool neg = (th >> 63) != 0;
-                const bool s1pos = (xs != a) != neg;
-                const bool s2pos = (xd != b);
-                const uint32_t T = (s1pos && s2pos) ? tp : ((!s1pos && !s2pos) ? tm : (1u << 23));
-                if (U[j] >= T) zbits |= (1ull << dd);
+    for (int r = 0; r < NREG; ++r) outr[r] = 0u;
+    const bool leader = live && (lm.lane % LPI == 0);
+    int a = 1, b = 1;
+#pragma unroll
+    for (int k = 0; k < NCALL; ++k) {
+        if (!UQ && __ballot(5 * k < De) == 0) break;
+        const Words w = philox4x32_10(ulo, uhi, (kPhaseDual << 30) | (uint32_t)(16 * lm.c + k), t,
+                                      g.k0, g.k1);
+        const uint32_t W[5] = {w.w0, w.w1, w.w2, w.w3,
+                               (w.w0 << 24) | ((w.w1 & 0xFFu) << 16) | ((w.w2 & 0xFFu) << 8)};
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int dd = 5 * k + j;
+            if (dd >= D) break;
+            // k = sigma (1 - 2y) + (1 - 2y'):  +2 on kp, -2 on km, 0 elsewhere
+            const uint64_t ya = UQ ? mya[dd / (QM - 1) + 1] : __ballot(xs == a);
+            const uint64_t yb = UQ ? myb[dd % (QM - 1) + 1] : __ballot(xd == b);
+            const uint64_t neg = (LPI == 64) ? (0ull - ((sign >> dd) & 1ull))
+                                             : __ballot(((sign >> dd) & 1ull) != 0);
+            const uint64_t kp = ~yb & ~(ya ^ neg);
+            const uint64_t km = yb & (ya ^ neg);
+            const uint32_t tp8m1 = thr[2 * dd], tm8 = thr[2 * dd + 1];
+            const uint64_t cp = __ballot(W[j] > tp8m1);          // U >= T+
+            const uint64_t cm = __ballot(W[j] >= tm8);           // U >= T-
+            const uint64_t ch = __ballot(W[j] >= 0x80000000u);   // U >= 2^23
+            uint64_t zm = mact & ((kp & cp) | (km & cm) | (~(kp | km) & ch));
+            if (!UQ) zm &= __ballot(dd < De);
+            if (LPI == 64) {
+                outr[(2 * dd) >> 6] =
+                    pdg_writelane_i32((uint32_t)zm, (2 * dd) & 63, outr[(2 * dd) >> 6]);
+                outr[(2 * dd + 1) >> 6] = pdg_writelane_i32(
+                    (uint32_t)(zm >> 32), (2 * dd + 1) & 63, outr[(2 * dd + 1) >> 6]);
+            } else if (LPI == 32) {
+                outr[dd >> 6] = pdg_writelane_i32((uint32_t)zm, dd & 63, outr[dd >> 6]);
+                outr[(D + dd) >> 6] =
+                    pdg_writelane_i32((uint32_t)(zm >> 32), (D + dd) & 63, outr[(D + dd) >> 6]);
+            } else if (leader && (UQ || dd < De)) {
+                const int p0 = (lm.lane / LPI) * LPI;
+                g.z[(uint64_t)sl * D + dd] = (uint32_t)((zm >> p0) & ((1ull << (LPI & 31)) - 1ull));
+            }
+            if (!UQ) {
                 if (++b == qd) {
                     b = 1;
                     ++a;
@@ -237,143 +322,157 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
             }
         }
     }
-    // Bit-planes out: item p owns ballot bits [p LPI, (p+1) LPI).
-    const bool leader = live && ((LPI == 64) ? (lm.lane == 0) : (lm.lane % LPI == 0));
-    uint32_t *zs = g.z + (uint64_t)(in_range ? slot : 0) * D * g.Wz;
+    // Gathered plane words out.  LPI = 64: the 2D u32 halves of this chain
+    // block's D masks, contiguous; LPI = 32: word p D + d of item p (the
+    // wave's two slots are adjacent).
+    if (LPI >= 32) {
+        const uint64_t livemask = __ballot(live);
 #pragma unroll
-    for (int dd = 0; dd < D; ++dd) {
-        const uint64_t bal = __ballot((zbits >> dd) & 1ull);
-        if (leader) {
-            if (LPI == 64) {
-                uint2 wv;
-                wv.x = (uint32_t)bal;
-                wv.y = (uint32_t)(bal >> 32);
-                *reinterpret_cast<uint2 *>(zs + dd * g.Wz + 2 * lm.cb) = wv;
-            } else {
-                const int p0 = (lm.lane / LPI) * LPI;
-                const uint64_t mask = (LPI >= 32) ? 0xFFFFFFFFull : ((1ull << (LPI & 31)) - 1ull);
-                zs[dd * g.Wz] = (uint32_t)((bal >> p0) & mask);
+        for (int r = 0; r < NREG; ++r) {
+            const int idx = 64 * r + lm.lane;
+            if (idx < NW) {
+                if (LPI == 64) {
+                    if (live) g.z[((uint64_t)sl * g.CB + lm.cb) * 2 * D + idx] = outr[r];
+                } else {
+                    const int p = idx / D, dd = idx - p * D;
+                    if ((livemask >> (32 * p)) & 1ull) g.z[(uint64_t)(lm.base + p) * D + dd] = outr[r];
+                }
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// a4 + a5: primal phase and marginal counting.  Node i, chain c:
-//   L(a) = lam(a) + sum over incident edges of the field of state a,
-//   src side: c_row(a) + sum_b v_ab (1 - 2 theta_ab),
-//   dst side: c_col(b) + sum_a t_ab (1 - 2 theta_ab), t = -|v|;
-// then m = max L, w_a = e^(L(a) - m) (FP32 exp unless EXP64), F cumulative in
-// FP64, x = min{a : u F_{q-1} < F_a}, u = (U + 0.5) 2^-24 from call
-// (node, PRIMAL, c / 4, t), word c mod 4.
+// a4 + a5: primal phase and marginal counting.  Lane (node quad Q, chain c)
+// takes one generator call (Q, PRIMAL, c, t) and walks the quad's four nodes;
+// node 4Q + j draws with word j.  For node i:
+//   L(a) = lam(a) + sum over incident edges of the field of state a:
+//   src side c0_row(a) + sum_b 2 theta_ab h_ab, dst side c0_col(b) + sum_a 2 theta_ab |h_ab|;
+// then m = max L, weights e^(L(a) - m) (FP32 exp unless EXP64), F cumulative in
+// FP64, x = min{a : u F_{q-1} < F_a} with u = (U + 0.5) 2^-24.
+// With LPI = 64 a plane word pair is the lane mask of the chain block, so an
+// entry costs one select and one FP64 FMA.
 // ---------------------------------------------------------------------------
-template <int QM, int LPI, bool EXP64>
+template <int QM, int LPI, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
 {
     constexpr int D = dim_d(QM);
     const LaneMap<LPI> lm(g.C);
-    const int64_t node = lm.item;
-    const bool valid = node < g.n;
-    const bool active = valid && lm.c < g.C;
-    int newx = -1;
-    int qn = 0;
-    if (valid) {
-        qn = g.q[node];
-        double L[QM];
+    const int64_t quad = lm.item;
+    const bool cvalid = lm.c < g.C;
+    const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                   (kPhasePrimal << 30) | (uint32_t)lm.c, t, g.k0, g.k1);
+    const uint32_t Wn[4] = {wq.w0, wq.w1, wq.w2, wq.w3};
 #pragma unroll
-        for (int a = 0; a < QM; ++a) L[a] = 0.0;
-        const uint32_t off = g.inc_off[node], cnt = g.inc_cnt[node];
-        const int w = lm.c >> 5;
-        const uint32_t bit = (uint32_t)lm.c & 31u;
-        for (uint32_t k = 0; k < cnt; ++k) {
-            const uint32_t e = g.inc[off + k];
-            if (e == kTomb) continue;
-            const uint32_t slot = e >> 1;
-            const uint32_t sq = g.sq[slot];
-            const uint8_t *blk = g.params + (int64_t)slot * block_bytes(QM);
-            const double *v = reinterpret_cast<const double *>(blk + 8 * D);
-            const double *cc = reinterpret_cast<const double *>(blk + 16 * D);
-            const uint32_t *zs = g.z + (uint64_t)slot * D * g.Wz + w;
-            if ((e & 1u) == 0) {
-                const int qo = (int)(sq >> 4);
+    for (int j = 0; j < 4; ++j) {
+        const int64_t node = quad * 4 + j;
+        const bool nvalid = node < g.n;
+        const bool active = nvalid && cvalid;
+        int newx = -1;
+        int qn = 0;
+        if (nvalid) {
+            qn = UQ ? QM : (int)g.q[node];
+            double L[QM];
 #pragma unroll
-                for (int a = 1; a < QM; ++a) {
-                    if (a >= qn) break;
-                    double s = cc[a - 1];
+            for (int a = 0; a < QM; ++a) L[a] = 0.0;
+            const uint32_t off = g.inc_off[node], cnt = g.inc_cnt[node];
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const uint32_t e = g.inc[off + k];
+                if (e == kTomb) continue;
+                const uint32_t slot = e >> 1;
+                const uint8_t *blk = g.params + (int64_t)slot * block_bytes(QM);
+                const double *h = reinterpret_cast<const double *>(blk + off_h(QM));
+                const double *c0 = reinterpret_cast<const double *>(blk + off_c0(QM));
+                int qo = QM;
+                if (!UQ) {
+                    const uint32_t sq = g.sq[slot];
+                    qo = (e & 1u) ? (int)(sq & 15u) : (int)(sq >> 4);
+                }
+                // theta of entry d for this lane's chain
+                const uint64_t *zm64 = reinterpret_cast<const uint64_t *>(g.z) +
+                                       ((uint64_t)slot * g.CB + lm.cb) * D;
+                const uint32_t *zw32 = g.z + (uint64_t)slot * D;
+                auto theta = [&](int d) -> bool {
+                    if (LPI == 64) return lane_bit(zm64[d]);
+                    return ((zw32[d] >> (lm.c & 31)) & 1u) != 0;
+                };
+                // acc + 2 theta h in one FMA: zf is 0.0 or 2.0 (a select of
+                // inline constants) and 2 h is exact
+                auto add = [&](double acc, bool th, double hv) -> double {
+                    const double zf = __hiloint2double(th ? 0x40000000 : 0, 0);
+                    return __builtin_fma(zf, hv, acc);
+                };
+                if ((e & 1u) == 0) {  // node is the src endpoint: state a = s
 #pragma unroll
-                    for (int b = 1; b < QM; ++b) {
-                        if (b >= qo) break;
-                        const int d = (a - 1) * (qo - 1) + (b - 1);
-                        const uint32_t zb = (zs[d * g.Wz] >> bit) & 1u;
-                        const double vv = v[d];
-                        s += zb ? -vv : vv;
+                    for (int s = 1; s < QM; ++s) {
+                        if (!UQ && s >= qn) break;
+                        double acc = L[s] + c0[s - 1];
+#pragma unroll
+                        for (int o = 1; o < QM; ++o) {
+                            if (!UQ && o >= qo) break;
+                            const int d = (s - 1) * (UQ ? QM - 1 : qo - 1) + (o - 1);
+                            acc = add(acc, theta(d), h[d]);
+                        }
+                        L[s] = acc;
                     }
-                    L[a] += s;
-                }
-            } else {
-                const int qo = (int)(sq & 15u);
+                } else {  // node is the dst endpoint: state b = s
 #pragma unroll
-                for (int b = 1; b < QM; ++b) {
-                    if (b >= qn) break;
-                    double s = cc[(QM - 1) + b - 1];
+                    for (int s = 1; s < QM; ++s) {
+                        if (!UQ && s >= qn) break;
+                        double acc = L[s] + c0[(QM - 1) + s - 1];
 #pragma unroll
-                    for (int a = 1; a < QM; ++a) {
-                        if (a >= qo) break;
-                        const int d = (a - 1) * (qn - 1) + (b - 1);
-                        const uint32_t zb = (zs[d * g.Wz] >> bit) & 1u;
-                        const double tt = -fabs(v[d]);
-                        s += zb ? -tt : tt;
+                        for (int o = 1; o < QM; ++o) {
+                            if (!UQ && o >= qo) break;
+                            const int d = (o - 1) * (UQ ? QM - 1 : qn - 1) + (s - 1);
+                            acc = add(acc, theta(d), fabs(h[d]));
+                        }
+                        L[s] = acc;
                     }
-                    L[b] += s;
                 }
             }
-        }
-        const double *lam = g.lam + node * QM;
+            const double *lam = g.lam + node * QM;
 #pragma unroll
-        for (int a = 0; a < QM; ++a)
-            if (a < qn) L[a] += lam[a];
-        double mx = L[0];
+            for (int a = 0; a < QM; ++a)
+                if (UQ || a < qn) L[a] += lam[a];
+            double mx = L[0];
 #pragma unroll
-        for (int a = 1; a < QM; ++a)
-            if (a < qn) mx = fmax(mx, L[a]);
-        double F[QM];
-        double acc = 0.0;
+            for (int a = 1; a < QM; ++a)
+                if (UQ || a < qn) mx = fmax(mx, L[a]);
+            double F[QM];
+            double acc = 0.0;
 #pragma unroll
-        for (int a = 0; a < QM; ++a) {
-            if (a < qn) {
-                double wgt;
-                if (EXP64) {
-                    wgt = exp(L[a] - mx);
-                } else {
-                    wgt = (double)exp2f((float)((L[a] - mx) * 1.4426950408889634074));
+            for (int a = 0; a < QM; ++a) {
+                if (UQ || a < qn) {
+                    double wgt;
+                    if (EXP64)
+                        wgt = exp(L[a] - mx);
+                    else
+                        wgt = (double)exp2f((float)((L[a] - mx) * 1.4426950408889634074));
+                    acc += wgt;
                 }
-                acc += wgt;
+                F[a] = acc;
             }
-            F[a] = acc;
+            const uint32_t U = Wn[j] >> 8;
+            const double target = ((double)U + 0.5) * 5.9604644775390625e-08 * F[QM - 1];
+            newx = qn - 1;
+#pragma unroll
+            for (int a = QM - 1; a >= 0; --a)
+                if ((UQ || a < qn) && target < F[a]) newx = a;
+            if (active) g.x[node * g.C + lm.c] = (uint8_t)newx;
         }
-        const Words wd = philox4x32_10((uint32_t)node, (uint32_t)(node >> 32),
-                                       (kPhasePrimal << 30) | (uint32_t)(lm.c >> 2), t, g.k0,
-                                       g.k1);
-        const uint32_t U = word_at(wd, lm.c & 3) >> 8;
-        const double target = ((double)U + 0.5) * 5.9604644775390625e-08 * F[QM - 1];
-        newx = qn - 1;
+        if (count) {
+            const bool leader = nvalid && (lm.lane % LPI == 0);
 #pragma unroll
-        for (int a = QM - 1; a >= 0; --a)
-            if (a < qn && target < F[a]) newx = a;
-        if (active) g.x[node * g.C + lm.c] = (uint8_t)newx;
-    }
-    if (count) {
-        const bool leader = valid && ((LPI == 64) ? (lm.lane == 0) : (lm.lane % LPI == 0));
-#pragma unroll
-        for (int a = 0; a < QM; ++a) {
-            const uint64_t bal = __ballot(active && newx == a);
-            uint64_t mine = bal;
-            if (LPI < 64) {
-                const int p0 = (lm.lane / LPI) * LPI;
-                mine = (bal >> p0) & ((LPI >= 64) ? ~0ull : ((1ull << (LPI & 63)) - 1ull));
+            for (int a = 0; a < QM; ++a) {
+                const uint64_t bal = __ballot(active && newx == a);
+                uint64_t mine = bal;
+                if (LPI < 64) {
+                    const int p0 = (lm.lane / LPI) * LPI;
+                    mine = (bal >> p0) & ((LPI >= 64) ? ~0ull : ((1ull << (LPI & 63)) - 1ull));
+                }
+                if (leader && a < qn && mine != 0)
+                    atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(mine));
             }
-            if (leader && a < qn && mine != 0)
-                atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(mine));
         }
     }
 }
@@ -458,17 +557,16 @@ __global__ void k_scatter_nodes(int64_t m, const uint32_t *__restrict__ node,
 }
 
 // theta of m edges (given by slot) for every chain: out [m][C], bit d.
-__global__ void k_get_duals(int64_t m, int32_t C, int32_t D, int32_t Wz,
-                            const int32_t *__restrict__ slots, const uint32_t *__restrict__ z,
+__global__ void k_get_duals(int64_t m, int32_t D, Graph g, const int32_t *__restrict__ slots,
                             uint64_t *__restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= m * C) return;
-    const int64_t k = idx / C;
-    const int c = (int)(idx - k * C);
-    const uint32_t *zs = z + (uint64_t)slots[k] * D * Wz + (c >> 5);
+    if (idx >= m * g.C) return;
+    const int64_t k = idx / g.C;
+    const int c = (int)(idx - k * g.C);
     uint64_t bits = 0;
-    for (int d = 0; d < D; ++d) bits |= (uint64_t)((zs[d * Wz] >> (c & 31)) & 1u) << d;
+    for (int d = 0; d < D; ++d)
+        bits |= (uint64_t)((g.z[zword_index(g, slots[k], d, c, D)] >> (c & 31)) & 1u) << d;
     out[idx] = bits;
 }
 

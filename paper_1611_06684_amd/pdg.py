@@ -68,8 +68,7 @@ def lib():
             "pdg_num_edges": ([_P, ctypes.POINTER(_I64)], S),
             "pdg_live_uids": ([_P, _P], S),
             "pdg_decompose": ([_I64, _I32, _P, _P, _P, _I32, _P, _P], S),
-            "pdg_params_layout": ([_I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
-                                   ctypes.POINTER(_I64), ctypes.POINTER(_I64)], S),
+            "pdg_params_layout": ([_I32] + [ctypes.POINTER(_I64)] * 5, S),
             "pdg_init_chains": ([_P], S),
             "pdg_set_state": ([_P, _P], S),
             "pdg_get_state": ([_P, _P], S),
@@ -140,7 +139,8 @@ def pdg_decompose(m, q_max, d_qs, d_qd, d_log_phi, precision, d_params_out, stre
 
 
 def pdg_params_layout(q_max):
-    v = [_I64(0) for _ in range(4)]
+    """(bytes per edge, offset of sign, thr, h, c0)."""
+    v = [_I64(0) for _ in range(5)]
     _chk(lib().pdg_params_layout(q_max, *[ctypes.byref(x) for x in v]))
     return tuple(x.value for x in v)
 

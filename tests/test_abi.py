@@ -33,7 +33,8 @@ def test_library_exports_every_declared_symbol():
 def test_params_layout():
     for q in range(2, 9):
         D = (q - 1) ** 2
-        assert pdg.pdg_params_layout(q) == (16 * D + 16 * (q - 1), 0, 8 * D, 16 * D)
+        assert pdg.pdg_params_layout(q) == (8 + 16 * D + 16 * (q - 1), 0, 8, 8 + 8 * D,
+                                            8 + 16 * D)
     with pytest.raises(pdg.PdgError) as e:
         pdg.pdg_params_layout(9)
     assert e.value.code == pdg.PDG_EINVAL

@@ -126,15 +126,16 @@ def test_decompose_matches_oracle_conditionals():
         Lam[:5] *= 8.0  # large odds ratios
         Lam[5:10] *= 1e-7  # near-unit odds ratios
         dev = torch.device("cuda", 0)
-        bb, o_thr, o_v, o_c = pdg.pdg_params_layout(qm)
+        bb, o_sign, o_thr, o_h, o_c = pdg.pdg_params_layout(qm)
         out = torch.zeros(m * bb, dtype=torch.uint8, device=dev)
         tq = [torch.as_tensor(a, device=dev) for a in (qs, qd, Lam)]
         pdg.pdg_decompose(m, qm, tq[0].data_ptr(), tq[1].data_ptr(), tq[2].data_ptr(),
                           1 if f64 else 0, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
         blk = out.cpu().numpy().reshape(m, bb)
         D = (qm - 1) ** 2
-        thr = blk[:, o_thr:o_thr + 8 * D].copy().view(np.uint64)
-        v = blk[:, o_v:o_v + 8 * D].copy().view(np.float64)
+        sign = blk[:, o_sign:o_sign + 8].copy().view(np.uint64)[:, 0]
+        thr = blk[:, o_thr:o_thr + 8 * D].copy().view(np.uint32).reshape(m, D, 2)
+        w = 2.0 * blk[:, o_h:o_h + 8 * D].copy().view(np.float64)
         c = blk[:, o_c:o_c + 16 * (qm - 1)].copy().view(np.float64).reshape(m, 2, qm - 1)
         q = np.zeros(2 * m, np.int32)
         q[0::2], q[1::2] = qs, qd
@@ -146,18 +147,16 @@ def test_decompose_matches_oracle_conditionals():
             for a in range(1, qs[e]):
                 row_o = dec.rrow[e, a] + sum(dec.par[e, (a - 1) * (qd[e] - 1) + b - 1, 0]
                                              for b in range(1, qd[e]))
-                row_g = c[e, 0, a - 1] + sum(v[e, (a - 1) * (qd[e] - 1) + b - 1]
-                                            for b in range(1, qd[e]))
-                assert abs(row_o - row_g) < 1e-9 * (1 + abs(row_o)), (e, a, row_o, row_g)
+                assert abs(row_o - c[e, 0, a - 1]) < 1e-9 * (1 + abs(row_o)), (e, a)
                 for b in range(1, qd[e]):
                     d = (a - 1) * (qd[e] - 1) + (b - 1)
                     par = dec.par[e, d]
-                    tscale = 1e-9 * (1 + abs(par[3]))
-                    assert abs(-2 * v[e, d] - par[3]) < tscale
-                    assert abs(2 * abs(v[e, d]) - par[4]) < 1e-9 * (1 + abs(par[4]))
-                    neg = bool(int(thr[e, d]) >> 63)
-                    tp = int(thr[e, d]) & 0x1FFFFFF
-                    tm = (int(thr[e, d]) >> 32) & 0x1FFFFFF
+                    assert abs(w[e, d] - par[3]) < 1e-9 * (1 + abs(par[3]))
+                    assert abs(abs(w[e, d]) - par[4]) < 1e-9 * (1 + abs(par[4]))
+                    neg = bool((int(sign[e]) >> d) & 1)
+                    tp = (int(thr[e, d, 0]) + 1) // 256
+                    tm = int(thr[e, d, 1]) // 256
+                    assert (int(thr[e, d, 0]) + 1) % 256 == 0 and int(thr[e, d, 1]) % 256 == 0
                     for y in (0, 1):
                         for yp in (0, 1):
                             s1 = (1 - 2 * y) * (-1 if neg else 1)
@@ -174,9 +173,7 @@ def test_decompose_matches_oracle_conditionals():
             for b in range(1, qd[e]):
                 col_o = dec.rcol[e, b] + sum(dec.par[e, (a - 1) * (qd[e] - 1) + b - 1, 1]
                                              for a in range(1, qs[e]))
-                col_g = c[e, 1, b - 1] - sum(abs(v[e, (a - 1) * (qd[e] - 1) + b - 1])
-                                            for a in range(1, qs[e]))
-                assert abs(col_o - col_g) < 1e-9 * (1 + abs(col_o)), (e, b, col_o, col_g)
+                assert abs(col_o - c[e, 1, b - 1]) < 1e-9 * (1 + abs(col_o)), (e, b)
         _say(f"  q_max={qm}: thresholds exact {n_exact}, on an integer boundary {n_edge}")
 
 

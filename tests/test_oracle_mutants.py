@@ -44,7 +44,7 @@ MUTANTS = {
     "cdf_not_normalised": ("if (u * F[qn - 1] < F[a]) { x = a; break; }",
                            "if (u < F[a]) { x = a; break; }"),
     "cdf_not_cumulative": ("F[a] = acc;", "F[a] = exp(L[a] - mx);"),
-    "primal_chain_quad": ("(uint32_t)(c / 4), t, c % 4);", "(uint32_t)(c / 4), t, 0);"),
+    "primal_node_quad_word": ("(int)(node % 4));", "(int)(c % 4));"),
     "init_floor": ("x[i * C + c] = (uint8_t)floor(u * q[i]);",
                    "x[i * C + c] = (uint8_t)floor(u * (q[i] - 1));"),
 }

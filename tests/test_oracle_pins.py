@@ -299,7 +299,7 @@ def test_equal_weights_draw_is_floor_uq():
     _, _, x_out, _ = oracle.sweep(m, dec, np.array([4], np.uint64), 9, 2, x_in)
     for i in range(2):
         for c in range(C):
-            u = oracle.uniform(9, oracle.PHASE_PRIMAL, i, c // 4, 2, c % 4)
+            u = oracle.uniform(9, oracle.PHASE_PRIMAL, i // 4, c, 2, i % 4)
             assert x_out[i, c] == int(np.floor(u * q))
 
 
