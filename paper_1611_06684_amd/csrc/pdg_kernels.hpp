@@ -556,7 +556,9 @@ __global__ void k_scatter_nodes(int64_t m, const uint32_t *__restrict__ node,
     }
 }
 
-// theta of m edges (given by slot) for every chain: out [m][C], bit d.
+// theta of m edges (given by slot) for every chain: out [m][C], bit d for the
+// edge's own entries d < (q_src-1)(q_dst-1); planes beyond them are not part of
+// the edge and are never read.
 __global__ void k_get_duals(int64_t m, int32_t D, Graph g, const int32_t *__restrict__ slots,
                             uint64_t *__restrict__ out)
 {
@@ -564,9 +566,12 @@ __global__ void k_get_duals(int64_t m, int32_t D, Graph g, const int32_t *__rest
     if (idx >= m * g.C) return;
     const int64_t k = idx / g.C;
     const int c = (int)(idx - k * g.C);
+    const int64_t s = slots[k];
+    const uint32_t sq = g.sq[s];
+    const int De = (int)((sq & 15u) - 1u) * (int)((sq >> 4) - 1u);
     uint64_t bits = 0;
-    for (int d = 0; d < D; ++d)
-        bits |= (uint64_t)((g.z[zword_index(g, slots[k], d, c, D)] >> (c & 31)) & 1u) << d;
+    for (int d = 0; d < De && d < D; ++d)
+        bits |= (uint64_t)((g.z[zword_index(g, s, d, c, D)] >> (c & 31)) & 1u) << d;
     out[idx] = bits;
 }
 
