@@ -153,7 +153,7 @@ def test_decompose_matches_oracle_conditionals():
                     par = dec.par[e, d]
                     assert abs(w[e, d] - par[3]) < 1e-9 * (1 + abs(par[3]))
                     assert abs(abs(w[e, d]) - par[4]) < 1e-9 * (1 + abs(par[4]))
-                    neg = bool((int(sign[e]) >> d) & 1)
+                    neg = bool((int(sign[e]) >> int(d)) & 1)
                     tp = (int(thr[e, d, 0]) + 1) // 256
                     tm = int(thr[e, d, 1]) // 256
                     assert (int(thr[e, d, 0]) + 1) % 256 == 0 and int(thr[e, d, 1]) % 256 == 0
