@@ -43,7 +43,9 @@ struct pdg_ctx {
     pdg_config cfg{};
     int device = 0;
     hipStream_t stream = nullptr;
-    int QM = 0, D = 0, C = 0, Wz = 0, LPI = 0, CB = 0;
+    int QM = 0, D = 0, C = 0, LPI = 0, CB = 0;
+    int RP = 0;       // doubles per incidence record
+    int64_t ZW = 0;   // u32 mask words per incidence record
     int64_t bbytes = 0;
     int64_t n = 0;
     bool nodes_set = false;
@@ -60,9 +62,11 @@ struct pdg_ctx {
     uint64_t *d_uid = nullptr;
     uint8_t *d_sq = nullptr;
     uint8_t *d_params = nullptr;
-    uint32_t *d_z = nullptr;
+    uint32_t *d_ipos = nullptr;
     uint32_t *d_off = nullptr, *d_cnt = nullptr;
     uint32_t *d_pool = nullptr;
+    double *d_rec_p = nullptr;
+    uint32_t *d_rec_z = nullptr;
     int64_t dev_pool_cap = 0;
     uint32_t *d_flag = nullptr;
     void *d_scratch = nullptr;
@@ -167,10 +171,12 @@ static Graph make_graph(pdg_ctx *ctx)
     g.uid = ctx->d_uid;
     g.sq = ctx->d_sq;
     g.params = ctx->d_params;
-    g.z = ctx->d_z;
+    g.ipos = ctx->d_ipos;
     g.inc_off = ctx->d_off;
     g.inc_cnt = ctx->d_cnt;
     g.inc = ctx->d_pool;
+    g.rec_p = ctx->d_rec_p;
+    g.rec_z = ctx->d_rec_z;
     g.x = ctx->d_x;
     g.counts = ctx->d_counts;
     g.n = ctx->n;
@@ -346,9 +352,21 @@ static uint32_t slack_for(uint32_t k) { return std::max<uint32_t>(2u, k / 4u); }
 
 struct Patches {
     std::vector<uint32_t> idx, val;        // pool entries
-    std::vector<uint32_t> node, off, cnt;  // node segment headers
-    bool full = false;                     // whole pool and every header
+    bool full = false;                     // whole pool and every header re-laid
+    std::vector<uint32_t> mv_from, mv_to;  // incidence records that moved
+    std::vector<uint32_t> ip_key, ip_val;  // ipos[2 slot + side] = record index
 };
+
+static void note_entry(Store &st, uint32_t e, uint32_t w, uint32_t rec, Patches &P)
+{
+    const uint32_t slot = e >> 1;
+    if (e & 1u)
+        st.pos1[slot] = w;
+    else
+        st.pos0[slot] = w;
+    P.ip_key.push_back(2u * slot + (e & 1u));
+    P.ip_val.push_back(rec);
+}
 
 // Lay every node's live entries out again, leaving room for `need` appends.
 static pdg_status full_compact(pdg_ctx *ctx, const std::vector<uint32_t> &need, Patches &P)
@@ -366,17 +384,20 @@ static pdg_status full_compact(pdg_ctx *ctx, const std::vector<uint32_t> &need, 
     const uint64_t size = total + total / 4 + 1024;
     if (size >= 0xFFFFFFF0ull) return fail(ctx, PDG_ECAPACITY, "incidence pool exceeds 2^32 entries");
     std::vector<uint32_t> npool((size_t)size, kTomb);
+    P.full = true;
+    P.idx.clear();
+    P.val.clear();
+    P.mv_from.clear();
+    P.mv_to.clear();
     for (int64_t i = 0; i < n; ++i) {
         uint32_t w = 0;
         for (uint32_t k = 0; k < st.cnt[i]; ++k) {
             const uint32_t e = st.pool[st.off[i] + k];
             if (e == kTomb) continue;
             npool[noff[i] + w] = e;
-            const uint32_t slot = e >> 1;
-            if (e & 1u)
-                st.pos1[slot] = w;
-            else
-                st.pos0[slot] = w;
+            P.mv_from.push_back(st.off[i] + k);
+            P.mv_to.push_back(noff[i] + w);
+            note_entry(st, e, w, noff[i] + w, P);
             ++w;
         }
         st.off[i] = noff[i];
@@ -385,9 +406,6 @@ static pdg_status full_compact(pdg_ctx *ctx, const std::vector<uint32_t> &need, 
     }
     st.pool.swap(npool);
     st.pool_top = (int64_t)total;
-    P.full = true;
-    P.idx.clear();
-    P.val.clear();
     return PDG_OK;
 }
 
@@ -403,15 +421,11 @@ static void relocate(pdg_ctx *ctx, int64_t i, uint32_t need, Patches &P)
         const uint32_t e = st.pool[st.off[i] + k];
         if (e == kTomb) continue;
         st.pool[noff + w] = e;
-        if (!P.full) {
-            P.idx.push_back(noff + w);
-            P.val.push_back(e);
-        }
-        const uint32_t slot = e >> 1;
-        if (e & 1u)
-            st.pos1[slot] = w;
-        else
-            st.pos0[slot] = w;
+        P.idx.push_back(noff + w);
+        P.val.push_back(e);
+        P.mv_from.push_back(st.off[i] + k);
+        P.mv_to.push_back(noff + w);
+        note_entry(st, e, w, noff + w, P);
         ++w;
     }
     st.off[i] = noff;
@@ -428,40 +442,31 @@ static void append(pdg_ctx *ctx, int64_t i, uint32_t e, Patches &P)
         P.idx.push_back(st.off[i] + p);
         P.val.push_back(e);
     }
-    const uint32_t slot = e >> 1;
-    if (e & 1u)
-        st.pos1[slot] = p;
-    else
-        st.pos0[slot] = p;
+    note_entry(st, e, p, st.off[i] + p, P);
     st.nlive[i]++;
 }
 
-// Push host-side changes of the incidence structure to the device.
+// Upload a host vector to a fresh region of the scratch buffer.
+template <typename T>
+static T *stage(pdg_ctx *ctx, char *&cursor, const std::vector<T> &v)
+{
+    T *p = reinterpret_cast<T *>(cursor);
+    if (!v.empty())
+        (void)hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream);
+    cursor += ((v.size() * sizeof(T) + 255) / 256) * 256;
+    return p;
+}
+
+// Push host-side changes of the incidence structure and its records to the
+// device: record moves (into new buffers after a full re-layout), pool
+// entries, segment headers and ipos.
 static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &touched)
 {
     Store &st = ctx->st;
-    if (P.full) {
-        if ((int64_t)st.pool.size() > ctx->dev_pool_cap) {
-            PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            if (ctx->d_pool) PDG_HIP(ctx, hipFree(ctx->d_pool));
-            ctx->d_pool = nullptr;
-            ctx->dev_pool_cap = 0;
-            PDG_TRY(dalloc(ctx, (void **)&ctx->d_pool, (int64_t)st.pool.size() * 4));
-            ctx->dev_pool_cap = (int64_t)st.pool.size();
-        }
-        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_pool, st.pool.data(), st.pool.size() * 4,
-                                    hipMemcpyHostToDevice, ctx->stream));
-        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_off, st.off.data(), (size_t)ctx->n * 4,
-                                    hipMemcpyHostToDevice, ctx->stream));
-        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_cnt, st.cnt.data(), (size_t)ctx->n * 4,
-                                    hipMemcpyHostToDevice, ctx->stream));
-        PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        return PDG_OK;
-    }
-    if (st.pool_top > ctx->dev_pool_cap)
-        return fail(ctx, PDG_EINVAL, "internal: pool beyond device capacity without full upload");
+    const int64_t nmv = (int64_t)P.mv_from.size();
     const int64_t np = (int64_t)P.idx.size();
     const int64_t nn = (int64_t)touched.size();
+    const int64_t nip = (int64_t)P.ip_key.size();
     std::vector<uint32_t> hn(nn), ho(nn), hc(nn);
     for (int64_t k = 0; k < nn; ++k) {
         hn[k] = (uint32_t)touched[k];
@@ -469,20 +474,67 @@ static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &t
         hc[k] = st.cnt[touched[k]];
     }
     void *s;
-    PDG_TRY(scratch(ctx, 4 * (2 * np + 3 * nn) + 64, &s));
-    uint32_t *di = (uint32_t *)s, *dv = di + np, *dn = dv + np, *dof = dn + nn, *dc = dof + nn;
-    if (np) {
-        PDG_HIP(ctx, hipMemcpyAsync(di, P.idx.data(), np * 4, hipMemcpyHostToDevice, ctx->stream));
-        PDG_HIP(ctx, hipMemcpyAsync(dv, P.val.data(), np * 4, hipMemcpyHostToDevice, ctx->stream));
-        k_scatter_u32<<<grid_for(np), 256, 0, ctx->stream>>>(np, di, dv, ctx->d_pool);
+    PDG_TRY(scratch(ctx, 4 * (2 * nmv + 2 * np + 3 * nn + 2 * nip) + 8 * 256, &s));
+    char *cur = static_cast<char *>(s);
+    uint32_t *dmf = stage(ctx, cur, P.mv_from), *dmt = stage(ctx, cur, P.mv_to);
+    uint32_t *di = stage(ctx, cur, P.idx), *dv = stage(ctx, cur, P.val);
+    uint32_t *dn = stage(ctx, cur, hn), *dof = stage(ctx, cur, ho), *dc = stage(ctx, cur, hc);
+    uint32_t *dk = stage(ctx, cur, P.ip_key), *dkv = stage(ctx, cur, P.ip_val);
+    PDG_HIP(ctx, hipGetLastError());
+    if (P.full) {
+        // new pool, records moved into fresh buffers
+        const int64_t cap = (int64_t)st.pool.size();
+        uint32_t *npool = nullptr;
+        double *nrp = nullptr;
+        uint32_t *nrz = nullptr;
+        PDG_TRY(dalloc(ctx, (void **)&npool, cap * 4));
+        pdg_status a = dalloc(ctx, (void **)&nrp, cap * ctx->RP * 8);
+        if (a == PDG_OK) a = dalloc(ctx, (void **)&nrz, cap * ctx->ZW * 4);
+        if (a != PDG_OK) {
+            (void)hipFree(npool);
+            if (nrp) (void)hipFree(nrp);
+            return a;
+        }
+        PDG_HIP(ctx, hipMemsetAsync(nrp, 0, cap * ctx->RP * 8, ctx->stream));
+        PDG_HIP(ctx, hipMemsetAsync(nrz, 0, cap * ctx->ZW * 4, ctx->stream));
+        if (nmv && ctx->d_rec_p) {
+            k_move_rec_p<<<grid_for(nmv * ctx->RP), 256, 0, ctx->stream>>>(nmv, ctx->RP, dmf, dmt,
+                                                                          ctx->d_rec_p, nrp);
+            k_move_rec_z<<<grid_for(nmv * ctx->ZW), 256, 0, ctx->stream>>>(nmv, ctx->ZW, dmf, dmt,
+                                                                          ctx->d_rec_z, nrz);
+            PDG_HIP(ctx, hipGetLastError());
+        }
+        PDG_HIP(ctx, hipMemcpyAsync(npool, st.pool.data(), cap * 4, hipMemcpyHostToDevice,
+                                    ctx->stream));
+        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_off, st.off.data(), (size_t)ctx->n * 4,
+                                    hipMemcpyHostToDevice, ctx->stream));
+        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_cnt, st.cnt.data(), (size_t)ctx->n * 4,
+                                    hipMemcpyHostToDevice, ctx->stream));
+        PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->d_pool) PDG_HIP(ctx, hipFree(ctx->d_pool));
+        if (ctx->d_rec_p) PDG_HIP(ctx, hipFree(ctx->d_rec_p));
+        if (ctx->d_rec_z) PDG_HIP(ctx, hipFree(ctx->d_rec_z));
+        ctx->d_pool = npool;
+        ctx->d_rec_p = nrp;
+        ctx->d_rec_z = nrz;
+        ctx->dev_pool_cap = cap;
+    } else {
+        if (st.pool_top > ctx->dev_pool_cap)
+            return fail(ctx, PDG_EINVAL, "internal: pool beyond device capacity without re-layout");
+        if (nmv) {  // relocated segments land in unused pool space: no overlap
+            k_move_rec_p<<<grid_for(nmv * ctx->RP), 256, 0, ctx->stream>>>(
+                nmv, ctx->RP, dmf, dmt, ctx->d_rec_p, ctx->d_rec_p);
+            k_move_rec_z<<<grid_for(nmv * ctx->ZW), 256, 0, ctx->stream>>>(
+                nmv, ctx->ZW, dmf, dmt, ctx->d_rec_z, ctx->d_rec_z);
+        }
+        if (np) k_scatter_u32<<<grid_for(np), 256, 0, ctx->stream>>>(np, di, dv, ctx->d_pool);
+        if (nn)
+            k_scatter_nodes<<<grid_for(nn), 256, 0, ctx->stream>>>(nn, dn, dof, dc, ctx->d_off,
+                                                                   ctx->d_cnt);
         PDG_HIP(ctx, hipGetLastError());
     }
-    if (nn) {
-        PDG_HIP(ctx, hipMemcpyAsync(dn, hn.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
-        PDG_HIP(ctx, hipMemcpyAsync(dof, ho.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
-        PDG_HIP(ctx, hipMemcpyAsync(dc, hc.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
-        k_scatter_nodes<<<grid_for(nn), 256, 0, ctx->stream>>>(nn, dn, dof, dc, ctx->d_off,
-                                                               ctx->d_cnt);
+    if (nip) {
+        k_set_ipos<<<grid_for(nip), 256, 0, ctx->stream>>>(nip, dk, dkv, ctx->d_ipos);
         PDG_HIP(ctx, hipGetLastError());
     }
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -491,9 +543,10 @@ static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &t
 
 static void free_all(pdg_ctx *ctx)
 {
-    void *ps[] = {ctx->d_q,   ctx->d_lam,    ctx->d_x,   ctx->d_counts, ctx->d_src,
-                  ctx->d_dst, ctx->d_uid,    ctx->d_sq,  ctx->d_params, ctx->d_z,
-                  ctx->d_off, ctx->d_cnt,    ctx->d_pool, ctx->d_flag,  ctx->d_scratch};
+    void *ps[] = {ctx->d_q,     ctx->d_lam,   ctx->d_x,     ctx->d_counts, ctx->d_src,
+                  ctx->d_dst,   ctx->d_uid,   ctx->d_sq,    ctx->d_params, ctx->d_ipos,
+                  ctx->d_off,   ctx->d_cnt,   ctx->d_pool,  ctx->d_rec_p,  ctx->d_rec_z,
+                  ctx->d_flag,  ctx->d_scratch};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -537,7 +590,8 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
     ctx->C = cfg->n_chains;
     ctx->LPI = choose_lpi(ctx->C);
     ctx->CB = (int)cdiv(ctx->C, ctx->LPI);
-    ctx->Wz = ctx->C <= 32 ? 1 : 2 * (int)cdiv(ctx->C, 64);
+    ctx->RP = rec_len(ctx->QM);
+    ctx->ZW = rec_words(ctx->QM, ctx->C);
     ctx->bbytes = block_bytes(ctx->QM);
     pdg_status s = PDG_OK;
     auto bail = [&](pdg_status code) {
@@ -558,7 +612,7 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
         (s = dalloc(ctx, (void **)&ctx->d_uid, S * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_sq, S)) ||
         (s = dalloc(ctx, (void **)&ctx->d_params, S * ctx->bbytes)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_z, S * (int64_t)ctx->D * ctx->Wz * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_ipos, S * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_off, N * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_cnt, N * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_flag, 64)))
@@ -714,7 +768,9 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
         append(ctx, hs[k], ((uint32_t)slots[k] << 1) | 0u, P);
         append(ctx, hd[k], ((uint32_t)slots[k] << 1) | 1u, P);
     }
-    // device: slot arrays, decomposition, incidence
+    // device: incidence structure and records (moves, ipos), then slot
+    // arrays, decomposition of the new tables, and their records
+    PDG_TRY(upload(ctx, P, touched));
     void *s;
     PDG_TRY(scratch(ctx, 8 * m + 4 * m * 3 + 64, &s));
     uint64_t *du = (uint64_t *)s;
@@ -729,8 +785,10 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     launch_decompose(ctx->QM, ctx->cfg.precision == PDG_PRECISION_F64, m, dqs, dqd, d_log_phi,
                      dslot, ctx->d_params, ctx->d_flag, ctx->stream);
     PDG_HIP(ctx, hipGetLastError());
+    k_write_records<<<grid_for(m * ctx->RP), 256, 0, ctx->stream>>>(
+        m, ctx->QM, dslot, ctx->d_sq, ctx->d_params, ctx->d_ipos, ctx->d_rec_p);
+    PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    PDG_TRY(upload(ctx, P, touched));
     return PDG_OK;
 }
 
@@ -759,6 +817,8 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
     }
     Patches P;
     std::vector<int64_t> touched;
+    std::vector<uint32_t> recs;
+    recs.reserve(2 * m);
     for (int64_t k = 0; k < m; ++k) {
         const int32_t s = slots[k];
         const int32_t a = st.src[s], b = st.dst[s];
@@ -769,18 +829,25 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
         P.val.push_back(kTomb);
         P.idx.push_back(ib);
         P.val.push_back(kTomb);
+        recs.push_back(ia);
+        recs.push_back(ib);
         st.nlive[a]--;
         st.nlive[b]--;
         st.free_stack.push_back(s);
     }
     st.live -= m;
+    PDG_TRY(upload(ctx, P, touched));
     void *sp;
-    PDG_TRY(scratch(ctx, 4 * m + 64, &sp));
-    PDG_HIP(ctx, hipMemcpyAsync(sp, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
-    k_slot_clear<<<grid_for(m), 256, 0, ctx->stream>>>(m, (const int32_t *)sp, ctx->d_uid);
+    PDG_TRY(scratch(ctx, 4 * m + 8 * m + 512, &sp));
+    int32_t *dsl = (int32_t *)sp;
+    uint32_t *drec = (uint32_t *)((char *)sp + ((4 * m + 255) / 256) * 256);
+    PDG_HIP(ctx, hipMemcpyAsync(dsl, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
+    PDG_HIP(ctx, hipMemcpyAsync(drec, recs.data(), 2 * m * 4, hipMemcpyHostToDevice, ctx->stream));
+    k_slot_clear<<<grid_for(m), 256, 0, ctx->stream>>>(m, dsl, ctx->d_uid);
+    k_clear_records<<<grid_for(2 * m * ctx->RP), 256, 0, ctx->stream>>>(2 * m, ctx->RP, drec,
+                                                                       ctx->d_rec_p);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    PDG_TRY(upload(ctx, P, touched));
     return PDG_OK;
 }
 
@@ -955,7 +1022,7 @@ pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_
     void *sp;
     PDG_TRY(scratch(ctx, 4 * m + 64, &sp));
     PDG_HIP(ctx, hipMemcpyAsync(sp, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
-    k_get_duals<<<grid_for(m * ctx->C), 256, 0, ctx->stream>>>(m, ctx->D, make_graph(ctx),
+    k_get_duals<<<grid_for(m * ctx->C), 256, 0, ctx->stream>>>(m, ctx->QM, make_graph(ctx),
                                                                (const int32_t *)sp, d_theta_out);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -11,13 +11,20 @@
 // Storage (device, all written by this library):
 //   x       uint8  [n][C]                 node states, chain fastest
 //   params  block  [slot]                 per-edge decomposition (layout below)
-//   z       [slot][chain block][D] words  dual bit-planes: with C <= 32 one
-//                                         32-bit word per (slot, d), bit c; with
-//                                         C > 32 one 64-bit word per (slot,
-//                                         block of 64 chains, d), bit c mod 64
 //   inc     uint32 pool                   per-node incidence segments
 //                                         [off, off + cnt): slot << 1 | side
 //                                         (side 0: node is src), or kTomb
+//   rec_p   double [pool][RP]             incidence records, RP = D + QM - 1:
+//                                         the side's h values (|h| on the dst
+//                                         side) in padded entry order
+//                                         d' = (a-1)(QM-1) + (b-1), then that
+//                                         side's c0; zero for tombstones
+//   rec_z   words  [pool][CB][D]          dual masks of each incidence record,
+//                                         padded order d': with C <= 32 a
+//                                         32-bit word per (record, d'), bit c;
+//                                         with C > 32 a 64-bit word per
+//                                         (record, block of 64 chains, d')
+//   ipos    uint32 [slot][2]              record index of the src / dst side
 //   counts  uint32 [n][QM]                marginal counters
 // Parameter block of an edge (QM = q_max, D = (QM-1)^2, entry d = (a-1)(q_dst-1)+(b-1)):
 //   sign  uint64          bit d set when the entry's log odds ratio is negative
@@ -56,10 +63,12 @@ struct Graph {
     const uint64_t *__restrict__ uid;     // [slots], 0 = free slot
     const uint8_t *__restrict__ sq;       // [slots] q_src | q_dst << 4
     const uint8_t *__restrict__ params;   // [slots] parameter blocks
-    uint32_t *__restrict__ z;             // dual bit-planes (layout above)
+    const uint32_t *__restrict__ ipos;    // [slots][2] record index per side
     const uint32_t *__restrict__ inc_off; // [n]
     const uint32_t *__restrict__ inc_cnt; // [n]
     const uint32_t *__restrict__ inc;     // pool
+    const double *__restrict__ rec_p;     // [pool][RP]
+    uint32_t *__restrict__ rec_z;         // [pool][CB][D] words
     uint8_t *__restrict__ x;              // [n][C]
     uint32_t *__restrict__ counts;        // [n][QM]
     int64_t n;
@@ -69,11 +78,18 @@ struct Graph {
     uint32_t k0, k1;                      // generator key
 };
 
-// u32 index of the plane word holding chain c of entry d of slot s.
-__device__ __forceinline__ uint64_t zword_index(const Graph &g, int64_t s, int d, int c, int D)
+__host__ __device__ constexpr int rec_len(int qm) { return dim_d(qm) + qm - 1; }
+// u32 words of dual masks per incidence record
+__host__ __device__ inline int64_t rec_words(int qm, int C)
 {
-    if (g.C <= 32) return (uint64_t)s * D + d;
-    return (((uint64_t)s * g.CB + (c >> 6)) * D + d) * 2 + ((c >> 5) & 1);
+    return C <= 32 ? (int64_t)dim_d(qm) : 2 * (int64_t)((C + 63) / 64) * dim_d(qm);
+}
+
+// u32 index of the mask word holding chain c of padded entry dp of record r.
+__device__ __forceinline__ uint64_t rec_zword(const Graph &g, uint64_t r, int dp, int c, int D)
+{
+    if (g.C <= 32) return r * D + dp;
+    return ((r * g.CB + (c >> 6)) * D + dp) * 2 + ((c >> 5) & 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -276,6 +292,8 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
 #pragma unroll
     for (int r = 0; r < NREG; ++r) outr[r] = 0u;
     const bool leader = live && (lm.lane % LPI == 0);
+    // records of the two endpoints receive the masks
+    const uint64_t r0 = live ? g.ipos[2 * sl] : 0ull, r1 = live ? g.ipos[2 * sl + 1] : 0ull;
     int a = 1, b = 1;
 #pragma unroll
     for (int k = 0; k < NCALL; ++k) {
@@ -312,7 +330,10 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
                     pdg_writelane_i32((uint32_t)(zm >> 32), (D + dd) & 63, outr[(D + dd) >> 6]);
             } else if (leader && (UQ || dd < De)) {
                 const int p0 = (lm.lane / LPI) * LPI;
-                g.z[(uint64_t)sl * D + dd] = (uint32_t)((zm >> p0) & ((1ull << (LPI & 31)) - 1ull));
+                const uint32_t wv = (uint32_t)((zm >> p0) & ((1ull << (LPI & 31)) - 1ull));
+                const int dp = UQ ? dd : (a - 1) * (QM - 1) + (b - 1);
+                g.rec_z[r0 * D + dp] = wv;
+                g.rec_z[r1 * D + dp] = wv;
             }
             if (!UQ) {
                 if (++b == qd) {
@@ -322,20 +343,47 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
             }
         }
     }
-    // Gathered plane words out.  LPI = 64: the 2D u32 halves of this chain
-    // block's D masks, contiguous; LPI = 32: word p D + d of item p (the
-    // wave's two slots are adjacent).
-    if (LPI >= 32) {
-        const uint64_t livemask = __ballot(live);
+    // Gathered mask words out to both records, padded entry order
+    // d' = (a-1)(QM-1) + (b-1) (= d when every node has q_max states).
+    // LPI = 64: lane 2d + h holds half h of entry d's mask of this chain block;
+    // LPI = 32: lane p D + d holds item p's word of entry d.
+    auto padded = [&](int dd, int qdv) -> int {
+        return (dd / (qdv - 1)) * (QM - 1) + dd % (qdv - 1);
+    };
+    if (LPI == 64) {
+        if (live) {
+            uint32_t *z0 = g.rec_z + (r0 * g.CB + lm.cb) * 2 * D;
+            uint32_t *z1 = g.rec_z + (r1 * g.CB + lm.cb) * 2 * D;
+#pragma unroll
+            for (int r = 0; r < NREG; ++r) {
+                const int idx = 64 * r + lm.lane;
+                const int dd = idx >> 1;
+                if (idx < NW && (UQ || dd < De)) {
+                    const int dp = UQ ? dd : padded(dd, qd);
+                    z0[2 * dp + (idx & 1)] = outr[r];
+                    z1[2 * dp + (idx & 1)] = outr[r];
+                }
+            }
+        }
+    } else if (LPI == 32) {
 #pragma unroll
         for (int r = 0; r < NREG; ++r) {
             const int idx = 64 * r + lm.lane;
             if (idx < NW) {
-                if (LPI == 64) {
-                    if (live) g.z[((uint64_t)sl * g.CB + lm.cb) * 2 * D + idx] = outr[r];
-                } else {
-                    const int p = idx / D, dd = idx - p * D;
-                    if ((livemask >> (32 * p)) & 1ull) g.z[(uint64_t)(lm.base + p) * D + dd] = outr[r];
+                const int p = idx / D, dd = idx - p * D;
+                const int64_t sp = lm.base + p;
+                if (sp < g.hwm && g.uid[sp] != 0) {
+                    int qdp = QM, Dep = D;
+                    if (!UQ) {
+                        const uint32_t sqp = g.sq[sp];
+                        qdp = (int)(sqp >> 4);
+                        Dep = ((int)(sqp & 15u) - 1) * (qdp - 1);
+                    }
+                    if (UQ || dd < Dep) {
+                        const int dp = UQ ? dd : padded(dd, qdp);
+                        g.rec_z[(uint64_t)g.ipos[2 * sp] * D + dp] = outr[r];
+                        g.rec_z[(uint64_t)g.ipos[2 * sp + 1] * D + dp] = outr[r];
+                    }
                 }
             }
         }
@@ -346,8 +394,9 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
 // a4 + a5: primal phase and marginal counting.  Lane (node quad Q, chain c)
 // takes one generator call (Q, PRIMAL, c, t) and walks the quad's four nodes;
 // node 4Q + j draws with word j.  For node i:
-//   L(a) = lam(a) + sum over incident edges of the field of state a:
-//   src side c0_row(a) + sum_b 2 theta_ab h_ab, dst side c0_col(b) + sum_a 2 theta_ab |h_ab|;
+//   L(a) = lam(a) + sum over the node's incidence records of the field of a:
+//   src side c0_row(a) + sum_b 2 theta_ab h_ab, dst side c0_col(b) + sum_a 2 theta_ab |h_ab|
+//   (records hold |h| on the dst side, padded entries and tombstones are zero);
 // then m = max L, weights e^(L(a) - m) (FP32 exp unless EXP64), F cumulative in
 // FP64, x = min{a : u F_{q-1} < F_a} with u = (U + 0.5) 2^-24.
 // With LPI = 64 a plane word pair is the lane mask of the chain block, so an
@@ -363,38 +412,35 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
     const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
                                    (kPhasePrimal << 30) | (uint32_t)lm.c, t, g.k0, g.k1);
     const uint32_t Wn[4] = {wq.w0, wq.w1, wq.w2, wq.w3};
+    // all four nodes are computed before anything is stored, so every load of
+    // the kernel precedes its stores (wave-uniform data stays on scalar loads)
+    int newx[4], qnv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t node = quad * 4 + j;
         const bool nvalid = node < g.n;
-        const bool active = nvalid && cvalid;
-        int newx = -1;
-        int qn = 0;
+        newx[j] = -1;
+        qnv[j] = 0;
         if (nvalid) {
+            int &qn = qnv[j];
             qn = UQ ? QM : (int)g.q[node];
             double L[QM];
 #pragma unroll
             for (int a = 0; a < QM; ++a) L[a] = 0.0;
+            // the node's incidence records are contiguous: [off, off + cnt)
             const uint32_t off = g.inc_off[node], cnt = g.inc_cnt[node];
             for (uint32_t k = 0; k < cnt; ++k) {
-                const uint32_t e = g.inc[off + k];
-                if (e == kTomb) continue;
-                const uint32_t slot = e >> 1;
-                const uint8_t *blk = g.params + (int64_t)slot * block_bytes(QM);
-                const double *h = reinterpret_cast<const double *>(blk + off_h(QM));
-                const double *c0 = reinterpret_cast<const double *>(blk + off_c0(QM));
-                int qo = QM;
-                if (!UQ) {
-                    const uint32_t sq = g.sq[slot];
-                    qo = (e & 1u) ? (int)(sq & 15u) : (int)(sq >> 4);
-                }
-                // theta of entry d for this lane's chain
-                const uint64_t *zm64 = reinterpret_cast<const uint64_t *>(g.z) +
-                                       ((uint64_t)slot * g.CB + lm.cb) * D;
-                const uint32_t *zw32 = g.z + (uint64_t)slot * D;
-                auto theta = [&](int d) -> bool {
-                    if (LPI == 64) return lane_bit(zm64[d]);
-                    return ((zw32[d] >> (lm.c & 31)) & 1u) != 0;
+                const uint64_t r = off + k;
+                // tombstones read as dst-side records whose values are all zero
+                const bool dst_side = (g.inc[r] & 1u) != 0;
+                const double *hp = g.rec_p + r * rec_len(QM);
+                const double *c0 = hp + D;
+                const uint64_t *zm64 =
+                    reinterpret_cast<const uint64_t *>(g.rec_z) + (r * g.CB + lm.cb) * D;
+                const uint32_t *zw32 = g.rec_z + r * D;
+                auto theta = [&](int dp) -> bool {
+                    if (LPI == 64) return lane_bit(zm64[dp]);
+                    return ((zw32[dp] >> (lm.c & 31)) & 1u) != 0;
                 };
                 // acc + 2 theta h in one FMA: zf is 0.0 or 2.0 (a select of
                 // inline constants) and 2 h is exact
@@ -402,29 +448,27 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
                     const double zf = __hiloint2double(th ? 0x40000000 : 0, 0);
                     return __builtin_fma(zf, hv, acc);
                 };
-                if ((e & 1u) == 0) {  // node is the src endpoint: state a = s
+                if (!dst_side) {  // node is the src endpoint: entries (s, o) of row s
 #pragma unroll
                     for (int s = 1; s < QM; ++s) {
                         if (!UQ && s >= qn) break;
                         double acc = L[s] + c0[s - 1];
 #pragma unroll
                         for (int o = 1; o < QM; ++o) {
-                            if (!UQ && o >= qo) break;
-                            const int d = (s - 1) * (UQ ? QM - 1 : qo - 1) + (o - 1);
-                            acc = add(acc, theta(d), h[d]);
+                            const int dp = (s - 1) * (QM - 1) + (o - 1);
+                            acc = add(acc, theta(dp), hp[dp]);
                         }
                         L[s] = acc;
                     }
-                } else {  // node is the dst endpoint: state b = s
+                } else {  // node is the dst endpoint: entries (o, s) of column s
 #pragma unroll
                     for (int s = 1; s < QM; ++s) {
                         if (!UQ && s >= qn) break;
-                        double acc = L[s] + c0[(QM - 1) + s - 1];
+                        double acc = L[s] + c0[s - 1];
 #pragma unroll
                         for (int o = 1; o < QM; ++o) {
-                            if (!UQ && o >= qo) break;
-                            const int d = (o - 1) * (UQ ? QM - 1 : qn - 1) + (s - 1);
-                            acc = add(acc, theta(d), fabs(h[d]));
+                            const int dp = (o - 1) * (QM - 1) + (s - 1);
+                            acc = add(acc, theta(dp), hp[dp]);
                         }
                         L[s] = acc;
                     }
@@ -454,23 +498,30 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
             }
             const uint32_t U = Wn[j] >> 8;
             const double target = ((double)U + 0.5) * 5.9604644775390625e-08 * F[QM - 1];
-            newx = qn - 1;
+            int xn = qn - 1;
 #pragma unroll
             for (int a = QM - 1; a >= 0; --a)
-                if ((UQ || a < qn) && target < F[a]) newx = a;
-            if (active) g.x[node * g.C + lm.c] = (uint8_t)newx;
+                if ((UQ || a < qn) && target < F[a]) xn = a;
+            newx[j] = xn;
         }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t node = quad * 4 + j;
+        const bool nvalid = node < g.n;
+        const bool active = nvalid && cvalid;
+        if (active) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
         if (count) {
             const bool leader = nvalid && (lm.lane % LPI == 0);
 #pragma unroll
             for (int a = 0; a < QM; ++a) {
-                const uint64_t bal = __ballot(active && newx == a);
+                const uint64_t bal = __ballot(active && newx[j] == a);
                 uint64_t mine = bal;
                 if (LPI < 64) {
                     const int p0 = (lm.lane / LPI) * LPI;
                     mine = (bal >> p0) & ((LPI >= 64) ? ~0ull : ((1ull << (LPI & 63)) - 1ull));
                 }
-                if (leader && a < qn && mine != 0)
+                if (leader && a < qnv[j] && mine != 0)
                     atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(mine));
             }
         }
@@ -557,9 +608,8 @@ __global__ void k_scatter_nodes(int64_t m, const uint32_t *__restrict__ node,
 }
 
 // theta of m edges (given by slot) for every chain: out [m][C], bit d for the
-// edge's own entries d < (q_src-1)(q_dst-1); planes beyond them are not part of
-// the edge and are never read.
-__global__ void k_get_duals(int64_t m, int32_t D, Graph g, const int32_t *__restrict__ slots,
+// edge's own entries d = (a-1)(q_dst-1) + (b-1), read from its src record.
+__global__ void k_get_duals(int64_t m, int32_t QM, Graph g, const int32_t *__restrict__ slots,
                             uint64_t *__restrict__ out)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -568,11 +618,87 @@ __global__ void k_get_duals(int64_t m, int32_t D, Graph g, const int32_t *__rest
     const int c = (int)(idx - k * g.C);
     const int64_t s = slots[k];
     const uint32_t sq = g.sq[s];
-    const int De = (int)((sq & 15u) - 1u) * (int)((sq >> 4) - 1u);
+    const int qs = (int)(sq & 15u), qd = (int)(sq >> 4);
+    const int D = (QM - 1) * (QM - 1);
+    const uint64_t r0 = g.ipos[2 * s];
     uint64_t bits = 0;
-    for (int d = 0; d < De && d < D; ++d)
-        bits |= (uint64_t)((g.z[zword_index(g, s, d, c, D)] >> (c & 31)) & 1u) << d;
+    for (int d = 0; d < (qs - 1) * (qd - 1); ++d) {
+        const int dp = (d / (qd - 1)) * (QM - 1) + d % (qd - 1);
+        bits |= (uint64_t)((g.rec_z[rec_zword(g, r0, dp, c, D)] >> (c & 31)) & 1u) << d;
+    }
     out[idx] = bits;
+}
+
+// New edges: copy h / c0 of the parameter block into both incidence records
+// (padded entry order; |h| on the dst side).  One thread per (edge, value).
+__global__ void k_write_records(int64_t m, int32_t QM, const int32_t *__restrict__ slots,
+                                const uint8_t *__restrict__ sq, const uint8_t *__restrict__ params,
+                                const uint32_t *__restrict__ ipos, double *__restrict__ rec_p)
+{
+    const int RP = rec_len(QM), D = dim_d(QM);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * RP) return;
+    const int64_t k = idx / RP;
+    const int j = (int)(idx - k * RP);
+    const int64_t s = slots[k];
+    const uint8_t *blk = params + s * block_bytes(QM);
+    const double *h = reinterpret_cast<const double *>(blk + off_h(QM));
+    const double *c0 = reinterpret_cast<const double *>(blk + off_c0(QM));
+    const int qs = (int)(sq[s] & 15u), qd = (int)(sq[s] >> 4);
+    double vs = 0.0, vd = 0.0;
+    if (j < D) {
+        const int a = j / (QM - 1) + 1, b = j % (QM - 1) + 1;
+        if (a < qs && b < qd) {
+            vs = h[(a - 1) * (qd - 1) + (b - 1)];
+            vd = fabs(vs);
+        }
+    } else {
+        vs = c0[j - D];
+        vd = c0[(QM - 1) + j - D];
+    }
+    rec_p[(uint64_t)ipos[2 * s] * RP + j] = vs;
+    rec_p[(uint64_t)ipos[2 * s + 1] * RP + j] = vd;
+}
+
+// Removed edges: zero their records (a zero record adds nothing to any field).
+__global__ void k_clear_records(int64_t m, int32_t RP, const uint32_t *__restrict__ rec,
+                                double *__restrict__ rec_p)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * RP) return;
+    const int64_t k = idx / RP;
+    rec_p[(uint64_t)rec[k] * RP + (idx - k * RP)] = 0.0;
+}
+
+// Moved incidence entries: record from[k] -> to[k] (u64 and u32 granules).
+__global__ void k_move_rec_p(int64_t m, int32_t RP, const uint32_t *__restrict__ from,
+                             const uint32_t *__restrict__ to, const double *__restrict__ src,
+                             double *__restrict__ dst)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * RP) return;
+    const int64_t k = idx / RP;
+    const int j = (int)(idx - k * RP);
+    dst[(uint64_t)to[k] * RP + j] = src[(uint64_t)from[k] * RP + j];
+}
+
+__global__ void k_move_rec_z(int64_t m, int64_t ZW, const uint32_t *__restrict__ from,
+                             const uint32_t *__restrict__ to, const uint32_t *__restrict__ src,
+                             uint32_t *__restrict__ dst)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * ZW) return;
+    const int64_t k = idx / ZW;
+    const int64_t j = idx - k * ZW;
+    dst[(uint64_t)to[k] * ZW + j] = src[(uint64_t)from[k] * ZW + j];
+}
+
+// ipos[key[k]] = val[k], key = 2 slot + side
+__global__ void k_set_ipos(int64_t m, const uint32_t *__restrict__ key,
+                           const uint32_t *__restrict__ val, uint32_t *__restrict__ ipos)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) ipos[key[k]] = val[k];
 }
 
 // live uids in slot order: out[k] for the k-th live slot (prefix given by host)
