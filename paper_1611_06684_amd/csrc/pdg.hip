@@ -185,6 +185,7 @@ static Graph make_graph(pdg_ctx *ctx)
     g.CB = (int32_t)cdiv(ctx->C, 64);
     g.k0 = (uint32_t)ctx->cfg.seed;
     g.k1 = (uint32_t)(ctx->cfg.seed >> 32);
+    g.rk = make_round_keys(ctx->cfg.seed);
     return g;
 }
 

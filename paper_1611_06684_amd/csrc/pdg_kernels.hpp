@@ -76,6 +76,7 @@ struct Graph {
     int32_t C;
     int32_t CB;                           // blocks of 64 chains (1 when C <= 64)
     uint32_t k0, k1;                      // generator key
+    RoundKeys rk;                         // its ten round keys
 };
 
 __host__ __device__ constexpr int rec_len(int qm) { return dim_d(qm) + qm - 1; }
@@ -299,26 +300,29 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
     for (int k = 0; k < NCALL; ++k) {
         if (!UQ && __ballot(5 * k < De) == 0) break;
         const Words w = philox4x32_10(ulo, uhi, (kPhaseDual << 30) | (uint32_t)(16 * lm.c + k), t,
-                                      g.k0, g.k1);
+                                      g.rk);
         const uint32_t W[5] = {w.w0, w.w1, w.w2, w.w3,
                                (w.w0 << 24) | ((w.w1 & 0xFFu) << 16) | ((w.w2 & 0xFFu) << 8)};
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             const int dd = 5 * k + j;
             if (dd >= D) break;
-            // k = sigma (1 - 2y) + (1 - 2y'):  +2 on kp, -2 on km, 0 elsewhere
+            // k = sigma (1 - 2y) + (1 - 2y') is +2 where yh = y ^ [sigma < 0] and y'
+            // are both 0, -2 where both are 1, else 0.  The compare masks nest
+            // (U >= T+ implies U >= 2^23 implies U >= T-), so
+            // theta = cp | (ch & (yh | y')) | (cm & yh & y').
+            // Lanes of absent chains produce bits that nothing reads.
             const uint64_t ya = UQ ? mya[dd / (QM - 1) + 1] : __ballot(xs == a);
             const uint64_t yb = UQ ? myb[dd % (QM - 1) + 1] : __ballot(xd == b);
             const uint64_t neg = (LPI == 64) ? (0ull - ((sign >> dd) & 1ull))
                                              : __ballot(((sign >> dd) & 1ull) != 0);
-            const uint64_t kp = ~yb & ~(ya ^ neg);
-            const uint64_t km = yb & (ya ^ neg);
+            const uint64_t yh = ya ^ neg;
             const uint32_t tp8m1 = thr[2 * dd], tm8 = thr[2 * dd + 1];
             const uint64_t cp = __ballot(W[j] > tp8m1);          // U >= T+
             const uint64_t cm = __ballot(W[j] >= tm8);           // U >= T-
             const uint64_t ch = __ballot(W[j] >= 0x80000000u);   // U >= 2^23
-            uint64_t zm = mact & ((kp & cp) | (km & cm) | (~(kp | km) & ch));
-            if (!UQ) zm &= __ballot(dd < De);
+            uint64_t zm = cp | (ch & (yh | yb)) | (cm & yh & yb);
+            if (!UQ) zm &= __ballot(dd < De) & mact;
             if (LPI == 64) {
                 outr[(2 * dd) >> 6] =
                     pdg_writelane_i32((uint32_t)zm, (2 * dd) & 63, outr[(2 * dd) >> 6]);
@@ -410,7 +414,7 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
     const int64_t quad = lm.item;
     const bool cvalid = lm.c < g.C;
     const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
-                                   (kPhasePrimal << 30) | (uint32_t)lm.c, t, g.k0, g.k1);
+                                   (kPhasePrimal << 30) | (uint32_t)lm.c, t, g.rk);
     const uint32_t Wn[4] = {wq.w0, wq.w1, wq.w2, wq.w3};
     // all four nodes are computed before anything is stored, so every load of
     // the kernel precedes its stores (wave-uniform data stays on scalar loads)
@@ -427,12 +431,10 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
             double L[QM];
 #pragma unroll
             for (int a = 0; a < QM; ++a) L[a] = 0.0;
-            // the node's incidence records are contiguous: [off, off + cnt)
+            // the node's incidence records are contiguous: [off, off + cnt);
+            // two records per step so their loads are in flight together
             const uint32_t off = g.inc_off[node], cnt = g.inc_cnt[node];
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const uint64_t r = off + k;
-                // tombstones read as dst-side records whose values are all zero
-                const bool dst_side = (g.inc[r] & 1u) != 0;
+            auto record = [&](uint64_t r, bool dst_side) {
                 const double *hp = g.rec_p + r * rec_len(QM);
                 const double *c0 = hp + D;
                 const uint64_t *zm64 =
@@ -448,31 +450,31 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
                     const double zf = __hiloint2double(th ? 0x40000000 : 0, 0);
                     return __builtin_fma(zf, hv, acc);
                 };
-                if (!dst_side) {  // node is the src endpoint: entries (s, o) of row s
 #pragma unroll
-                    for (int s = 1; s < QM; ++s) {
-                        if (!UQ && s >= qn) break;
-                        double acc = L[s] + c0[s - 1];
+                for (int s = 1; s < QM; ++s) {
+                    if (!UQ && s >= qn) break;
+                    double acc = L[s] + c0[s - 1];
 #pragma unroll
-                        for (int o = 1; o < QM; ++o) {
-                            const int dp = (s - 1) * (QM - 1) + (o - 1);
-                            acc = add(acc, theta(dp), hp[dp]);
-                        }
-                        L[s] = acc;
+                    for (int o = 1; o < QM; ++o) {
+                        // src side: entry (s, o) of row s; dst side: (o, s) of column s
+                        const int dp = dst_side ? (o - 1) * (QM - 1) + (s - 1)
+                                                : (s - 1) * (QM - 1) + (o - 1);
+                        acc = add(acc, theta(dp), hp[dp]);
                     }
-                } else {  // node is the dst endpoint: entries (o, s) of column s
-#pragma unroll
-                    for (int s = 1; s < QM; ++s) {
-                        if (!UQ && s >= qn) break;
-                        double acc = L[s] + c0[s - 1];
-#pragma unroll
-                        for (int o = 1; o < QM; ++o) {
-                            const int dp = (o - 1) * (QM - 1) + (s - 1);
-                            acc = add(acc, theta(dp), hp[dp]);
-                        }
-                        L[s] = acc;
-                    }
+                    L[s] = acc;
                 }
+            };
+            // tombstones read as dst-side records whose values are all zero
+            uint32_t k = 0;
+            for (; k + 1 < cnt; k += 2) {
+                const uint64_t r = off + k;
+                const bool d0 = (g.inc[r] & 1u) != 0, d1 = (g.inc[r + 1] & 1u) != 0;
+                if (d0) record(r, true); else record(r, false);
+                if (d1) record(r + 1, true); else record(r + 1, false);
+            }
+            if (k < cnt) {
+                const uint64_t r = off + k;
+                if (g.inc[r] & 1u) record(r, true); else record(r, false);
             }
             const double *lam = g.lam + node * QM;
 #pragma unroll
@@ -521,8 +523,12 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
                     const int p0 = (lm.lane / LPI) * LPI;
                     mine = (bal >> p0) & ((LPI >= 64) ? ~0ull : ((1ull << (LPI & 63)) - 1ull));
                 }
-                if (leader && a < qnv[j] && mine != 0)
-                    atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(mine));
+                if (leader && a < qnv[j] && mine != 0) {
+                    if (g.CB == 1)  // this wave owns the node: no other writer
+                        g.counts[node * QM + a] += (uint32_t)__popcll(mine);
+                    else
+                        atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(mine));
+                }
             }
         }
     }

@@ -41,6 +41,43 @@ __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return {c0, c1, c2, c3};
 }
 
+// Round keys of a launch: round r uses (k0 + r W0, k1 + r W1).  Computed once
+// on the host and passed in kernel arguments, so no lane recomputes them.
+struct RoundKeys {
+    uint32_t k0[10], k1[10];
+};
+
+__host__ inline RoundKeys make_round_keys(uint64_t seed)
+{
+    RoundKeys rk;
+    uint32_t a = (uint32_t)seed, b = (uint32_t)(seed >> 32);
+    for (int r = 0; r < 10; ++r) {
+        rk.k0[r] = a;
+        rk.k1[r] = b;
+        a += 0x9E3779B9u;
+        b += 0xBB67AE85u;
+    }
+    return rk;
+}
+
+// Same generator with the round keys supplied.
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, const RoundKeys &rk)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, rk.k0[r], 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, rk.k1[r], 0x96);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return {c0, c1, c2, c3};
+}
+
 // The fifth 24-bit integer of a call.
 __device__ __forceinline__ uint32_t fifth_u24(const Words &w)
 {
