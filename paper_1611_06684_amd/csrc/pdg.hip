@@ -604,22 +604,25 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
     };
     if (hipSetDevice(device) != hipSuccess) return bail(fail(ctx, PDG_EHIP, "hipSetDevice failed"));
     const int64_t N = cfg->node_capacity, S = cfg->edge_capacity;
+    const int64_t N4 = (N + 3) / 4 * 4;  // segment tables are read per node quad
     if ((s = dalloc(ctx, (void **)&ctx->d_q, N)) ||
         (s = dalloc(ctx, (void **)&ctx->d_lam, N * ctx->QM * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_x, N * ctx->C)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_counts, N * ctx->QM * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_counts, N4 * ctx->QM * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_src, S * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_dst, S * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_uid, S * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_sq, S)) ||
         (s = dalloc(ctx, (void **)&ctx->d_params, S * ctx->bbytes)) ||
         (s = dalloc(ctx, (void **)&ctx->d_ipos, S * 8)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_off, N * 4)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_cnt, N * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_off, N4 * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_cnt, N4 * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_flag, 64)))
         return bail(s);
     if (hipMemsetAsync(ctx->d_uid, 0, S * 8, ctx->stream) != hipSuccess ||
-        hipMemsetAsync(ctx->d_counts, 0, N * ctx->QM * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_off, 0, N4 * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_cnt, 0, N4 * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_counts, 0, N4 * ctx->QM * 4, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_x, 0, N * ctx->C, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)
         return bail(fail(ctx, PDG_EHIP, "initial clear failed"));

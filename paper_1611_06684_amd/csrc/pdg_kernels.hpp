@@ -14,16 +14,17 @@
 //   inc     uint32 pool                   per-node incidence segments
 //                                         [off, off + cnt): slot << 1 | side
 //                                         (side 0: node is src), or kTomb
-//   rec_p   double [pool][RP]             incidence records, RP = D + QM - 1:
-//                                         the side's h values (|h| on the dst
-//                                         side) in padded entry order
-//                                         d' = (a-1)(QM-1) + (b-1), then that
+//   rec_p   double [pool][RP]             incidence records, RP = D + QM - 1,
+//                                         in the node's orientation: entry
+//                                         (r-1)(QM-1) + (o-1) for own state r,
+//                                         other end's state o (h on the src
+//                                         side, |h| on the dst side), then the
 //                                         side's c0; zero for tombstones
 //   rec_z   words  [pool][CB][D]          dual masks of each incidence record,
-//                                         padded order d': with C <= 32 a
-//                                         32-bit word per (record, d'), bit c;
-//                                         with C > 32 a 64-bit word per
-//                                         (record, block of 64 chains, d')
+//                                         same entry order: with C <= 32 a
+//                                         32-bit word per (record, entry), bit
+//                                         c; with C > 32 a 64-bit word per
+//                                         (record, block of 64 chains, entry)
 //   ipos    uint32 [slot][2]              record index of the src / dst side
 //   counts  uint32 [n][QM]                marginal counters
 // Parameter block of an edge (QM = q_max, D = (QM-1)^2, entry d = (a-1)(q_dst-1)+(b-1)):
@@ -335,9 +336,9 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
             } else if (leader && (UQ || dd < De)) {
                 const int p0 = (lm.lane / LPI) * LPI;
                 const uint32_t wv = (uint32_t)((zm >> p0) & ((1ull << (LPI & 31)) - 1ull));
-                const int dp = UQ ? dd : (a - 1) * (QM - 1) + (b - 1);
-                g.rec_z[r0 * D + dp] = wv;
-                g.rec_z[r1 * D + dp] = wv;
+                const int ai = UQ ? dd / (QM - 1) : a - 1, bi = UQ ? dd % (QM - 1) : b - 1;
+                g.rec_z[r0 * D + ai * (QM - 1) + bi] = wv;
+                g.rec_z[r1 * D + bi * (QM - 1) + ai] = wv;
             }
             if (!UQ) {
                 if (++b == qd) {
@@ -347,12 +348,15 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
             }
         }
     }
-    // Gathered mask words out to both records, padded entry order
-    // d' = (a-1)(QM-1) + (b-1) (= d when every node has q_max states).
-    // LPI = 64: lane 2d + h holds half h of entry d's mask of this chain block;
-    // LPI = 32: lane p D + d holds item p's word of entry d.
+    // Gathered mask words out to both records, each in its node's orientation:
+    // (a-1)(QM-1) + (b-1) in the src record, (b-1)(QM-1) + (a-1) in the dst
+    // record.  LPI = 64: lane 2d + h holds half h of entry d's mask of this
+    // chain block; LPI = 32: lane p D + d holds item p's word of entry d.
     auto padded = [&](int dd, int qdv) -> int {
         return (dd / (qdv - 1)) * (QM - 1) + dd % (qdv - 1);
+    };
+    auto transposed = [&](int dd, int qdv) -> int {
+        return (dd % (qdv - 1)) * (QM - 1) + dd / (qdv - 1);
     };
     if (LPI == 64) {
         if (live) {
@@ -364,8 +368,9 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
                 const int dd = idx >> 1;
                 if (idx < NW && (UQ || dd < De)) {
                     const int dp = UQ ? dd : padded(dd, qd);
+                    const int dt = transposed(dd, UQ ? QM : qd);
                     z0[2 * dp + (idx & 1)] = outr[r];
-                    z1[2 * dp + (idx & 1)] = outr[r];
+                    z1[2 * dt + (idx & 1)] = outr[r];
                 }
             }
         }
@@ -385,8 +390,9 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
                     }
                     if (UQ || dd < Dep) {
                         const int dp = UQ ? dd : padded(dd, qdp);
+                        const int dt = transposed(dd, UQ ? QM : qdp);
                         g.rec_z[(uint64_t)g.ipos[2 * sp] * D + dp] = outr[r];
-                        g.rec_z[(uint64_t)g.ipos[2 * sp + 1] * D + dp] = outr[r];
+                        g.rec_z[(uint64_t)g.ipos[2 * sp + 1] * D + dt] = outr[r];
                     }
                 }
             }
@@ -399,25 +405,55 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
 // takes one generator call (Q, PRIMAL, c, t) and walks the quad's four nodes;
 // node 4Q + j draws with word j.  For node i:
 //   L(a) = lam(a) + sum over the node's incidence records of the field of a:
-//   src side c0_row(a) + sum_b 2 theta_ab h_ab, dst side c0_col(b) + sum_a 2 theta_ab |h_ab|
-//   (records hold |h| on the dst side, padded entries and tombstones are zero);
-// then m = max L, weights e^(L(a) - m) (FP32 exp unless EXP64), F cumulative in
-// FP64, x = min{a : u F_{q-1} < F_a} with u = (U + 0.5) 2^-24.
-// With LPI = 64 a plane word pair is the lane mask of the chain block, so an
-// entry costs one select and one FP64 FMA.
+//   src side c0_row(a) + sum_b 2 theta_ab h_ab, dst side c0_col(b) + sum_a 2 theta_ab |h_ab|;
+// a record is stored in the node's own orientation (row = the node's state),
+// so both sides read the same way; padded entries and tombstones are zero.
+// Then m = max L, weights e^(L(a) - m) (FP32 exp unless EXP64), F cumulative
+// in FP64, x = min{a : u F_{q-1} < F_a} with u = (U + 0.5) 2^-24.
+// With LPI = 64 a mask word pair is the lane mask of the chain block, so an
+// entry costs one select and one FP64 FMA; the quad's records are first
+// touched with vector loads (one pass, all lines in flight together) so the
+// scalar loads of the record walk hit L2.
 // ---------------------------------------------------------------------------
 template <int QM, int LPI, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
 {
     constexpr int D = dim_d(QM);
+    constexpr int RP = rec_len(QM);
     const LaneMap<LPI> lm(g.C);
     const int64_t quad = lm.item;
     const bool cvalid = lm.c < g.C;
     const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
                                    (kPhasePrimal << 30) | (uint32_t)lm.c, t, g.rk);
     const uint32_t Wn[4] = {wq.w0, wq.w1, wq.w2, wq.w3};
-    // all four nodes are computed before anything is stored, so every load of
-    // the kernel precedes its stores (wave-uniform data stays on scalar loads)
+    // segment table of the quad (the arrays are padded to a multiple of four
+    // nodes; entries past n are zero)
+    uint32_t off[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+    if (quad * 4 < g.n) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            off[j] = g.inc_off[quad * 4 + j];
+            cnt[j] = g.inc_cnt[quad * 4 + j];
+        }
+    }
+    const int64_t zstride = (LPI == 64) ? (int64_t)g.CB * D * 2 : (int64_t)D;  // u32 per record
+    uint32_t sink_p = 0, sink_z = 0;
+    if (LPI == 64) {
+        // lane (j, l): line l of node j's rec_p segment and of its rec_z segment
+        const int j = lm.lane >> 4, l = lm.lane & 15;
+        const uint32_t oj = j == 0 ? off[0] : j == 1 ? off[1] : j == 2 ? off[2] : off[3];
+        const uint32_t cj = j == 0 ? cnt[0] : j == 1 ? cnt[1] : j == 2 ? cnt[2] : cnt[3];
+        const uint64_t pb = (uint64_t)oj * (RP * 8), pe = pb + (uint64_t)cj * (RP * 8);
+        const uint64_t pa = (pb & ~(uint64_t)127) + 128 * (uint64_t)l;
+        if (pa < pe)
+            sink_p = *reinterpret_cast<const uint32_t *>(
+                reinterpret_cast<const uint8_t *>(g.rec_p) + pa);
+        const uint64_t zb = (uint64_t)oj * zstride * 4, ze = zb + (uint64_t)cj * zstride * 4;
+        const uint64_t za = (zb & ~(uint64_t)127) + 128 * (uint64_t)l;
+        if (za < ze)
+            sink_z = *reinterpret_cast<const uint32_t *>(
+                reinterpret_cast<const uint8_t *>(g.rec_z) + za);
+    }
     int newx[4], qnv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -431,24 +467,15 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
             double L[QM];
 #pragma unroll
             for (int a = 0; a < QM; ++a) L[a] = 0.0;
-            // the node's incidence records are contiguous: [off, off + cnt);
-            // two records per step so their loads are in flight together
-            const uint32_t off = g.inc_off[node], cnt = g.inc_cnt[node];
-            auto record = [&](uint64_t r, bool dst_side) {
-                const double *hp = g.rec_p + r * rec_len(QM);
+            const double *hp = g.rec_p + (uint64_t)off[j] * RP;
+            const uint32_t *zp = g.rec_z + (uint64_t)off[j] * zstride +
+                                 ((LPI == 64) ? (uint64_t)lm.cb * D * 2 : 0);
+            for (uint32_t k = 0; k < cnt[j]; ++k, hp += RP, zp += zstride) {
                 const double *c0 = hp + D;
-                const uint64_t *zm64 =
-                    reinterpret_cast<const uint64_t *>(g.rec_z) + (r * g.CB + lm.cb) * D;
-                const uint32_t *zw32 = g.rec_z + r * D;
                 auto theta = [&](int dp) -> bool {
-                    if (LPI == 64) return lane_bit(zm64[dp]);
-                    return ((zw32[dp] >> (lm.c & 31)) & 1u) != 0;
-                };
-                // acc + 2 theta h in one FMA: zf is 0.0 or 2.0 (a select of
-                // inline constants) and 2 h is exact
-                auto add = [&](double acc, bool th, double hv) -> double {
-                    const double zf = __hiloint2double(th ? 0x40000000 : 0, 0);
-                    return __builtin_fma(zf, hv, acc);
+                    if (LPI == 64)
+                        return lane_bit(reinterpret_cast<const uint64_t *>(zp)[dp]);
+                    return ((zp[dp] >> (lm.c & 31)) & 1u) != 0;
                 };
 #pragma unroll
                 for (int s = 1; s < QM; ++s) {
@@ -456,25 +483,14 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
                     double acc = L[s] + c0[s - 1];
 #pragma unroll
                     for (int o = 1; o < QM; ++o) {
-                        // src side: entry (s, o) of row s; dst side: (o, s) of column s
-                        const int dp = dst_side ? (o - 1) * (QM - 1) + (s - 1)
-                                                : (s - 1) * (QM - 1) + (o - 1);
-                        acc = add(acc, theta(dp), hp[dp]);
+                        // acc + 2 theta h in one FMA: the factor is 0.0 or 2.0
+                        // (a select of inline constants) and 2 h is exact
+                        const int dp = (s - 1) * (QM - 1) + (o - 1);
+                        const double zf = __hiloint2double(theta(dp) ? 0x40000000 : 0, 0);
+                        acc = __builtin_fma(zf, hp[dp], acc);
                     }
                     L[s] = acc;
                 }
-            };
-            // tombstones read as dst-side records whose values are all zero
-            uint32_t k = 0;
-            for (; k + 1 < cnt; k += 2) {
-                const uint64_t r = off + k;
-                const bool d0 = (g.inc[r] & 1u) != 0, d1 = (g.inc[r + 1] & 1u) != 0;
-                if (d0) record(r, true); else record(r, false);
-                if (d1) record(r + 1, true); else record(r + 1, false);
-            }
-            if (k < cnt) {
-                const uint64_t r = off + k;
-                if (g.inc[r] & 1u) record(r, true); else record(r, false);
             }
             const double *lam = g.lam + node * QM;
 #pragma unroll
@@ -506,6 +522,36 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
                 if ((UQ || a < qn) && target < F[a]) xn = a;
             newx[j] = xn;
         }
+    }
+    // the touch loads end here (their values are not used)
+    asm volatile("" ::"v"(sink_p), "v"(sink_z));
+    if (LPI == 64 && count && g.CB == 1) {
+        // The wave owns the quad's counters (the array is padded to whole
+        // quads): scalar-load them before any store, then store each node's
+        // row with one vector store (lane a holds state a).
+        uint32_t row[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool nvalid = quad * 4 + j < g.n;
+            row[j] = 0u;
+#pragma unroll
+            for (int a = 0; a < QM; ++a) {
+                const uint32_t v = g.counts[(quad * 4 + j) * QM + a] +
+                                   (uint32_t)__popcll(__ballot(nvalid && cvalid && newx[j] == a));
+                if (lm.lane == a) row[j] = v;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t node = quad * 4 + j;
+            if (node < g.n && cvalid) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t node = quad * 4 + j;
+            if (node < g.n && lm.lane < qnv[j]) g.counts[node * QM + lm.lane] = row[j];
+        }
+        return;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -635,8 +681,9 @@ __global__ void k_get_duals(int64_t m, int32_t QM, Graph g, const int32_t *__res
     out[idx] = bits;
 }
 
-// New edges: copy h / c0 of the parameter block into both incidence records
-// (padded entry order; |h| on the dst side).  One thread per (edge, value).
+// New edges: copy h / c0 of the parameter block into both incidence records,
+// each in its node's orientation (|h| on the dst side).  One thread per
+// (edge, value).
 __global__ void k_write_records(int64_t m, int32_t QM, const int32_t *__restrict__ slots,
                                 const uint8_t *__restrict__ sq, const uint8_t *__restrict__ params,
                                 const uint32_t *__restrict__ ipos, double *__restrict__ rec_p)
@@ -653,11 +700,10 @@ __global__ void k_write_records(int64_t m, int32_t QM, const int32_t *__restrict
     const int qs = (int)(sq[s] & 15u), qd = (int)(sq[s] >> 4);
     double vs = 0.0, vd = 0.0;
     if (j < D) {
-        const int a = j / (QM - 1) + 1, b = j % (QM - 1) + 1;
-        if (a < qs && b < qd) {
-            vs = h[(a - 1) * (qd - 1) + (b - 1)];
-            vd = fabs(vs);
-        }
+        // src record: row j / (QM-1) is the src state; dst record: the dst state
+        const int r = j / (QM - 1) + 1, o = j % (QM - 1) + 1;
+        if (r < qs && o < qd) vs = h[(r - 1) * (qd - 1) + (o - 1)];
+        if (o < qs && r < qd) vd = fabs(h[(o - 1) * (qd - 1) + (r - 1)]);
     } else {
         vs = c0[j - D];
         vd = c0[(QM - 1) + j - D];
