@@ -193,9 +193,15 @@ static Graph make_graph(pdg_ctx *ctx)
 template <int QM, int LPI, bool UQ>
 static void launch_dual_t(const Graph &g, uint32_t t, int CB, hipStream_t s)
 {
-    constexpr int P = 64 / LPI;
-    const int64_t waves = cdiv(g.hwm, P) * CB;
-    k_dual<QM, LPI, UQ><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+    if constexpr (LPI == 64) {
+        constexpr int E = kDualEdgesPerWave;
+        const int64_t waves = cdiv(g.hwm, E) * CB;
+        k_dual64<QM, UQ, E><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+    } else {
+        constexpr int P = 64 / LPI;
+        const int64_t waves = cdiv(g.hwm, P) * CB;
+        k_dual<QM, LPI, UQ><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+    }
 }
 
 template <int QM, int LPI, bool UQ, bool E64>
@@ -605,21 +611,27 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
     if (hipSetDevice(device) != hipSuccess) return bail(fail(ctx, PDG_EHIP, "hipSetDevice failed"));
     const int64_t N = cfg->node_capacity, S = cfg->edge_capacity;
     const int64_t N4 = (N + 3) / 4 * 4;  // segment tables are read per node quad
+    // slot arrays are read in groups of kDualEdgesPerWave slots
+    const int64_t SP = (S + kDualEdgesPerWave - 1) / kDualEdgesPerWave * kDualEdgesPerWave;
     if ((s = dalloc(ctx, (void **)&ctx->d_q, N)) ||
         (s = dalloc(ctx, (void **)&ctx->d_lam, N * ctx->QM * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_x, N * ctx->C)) ||
         (s = dalloc(ctx, (void **)&ctx->d_counts, N4 * ctx->QM * 4)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_src, S * 4)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_dst, S * 4)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_uid, S * 8)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_sq, S)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_params, S * ctx->bbytes)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_ipos, S * 8)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_src, SP * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_dst, SP * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_uid, SP * 8)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_sq, SP)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_params, SP * ctx->bbytes)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_ipos, SP * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_off, N4 * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_cnt, N4 * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_flag, 64)))
         return bail(s);
-    if (hipMemsetAsync(ctx->d_uid, 0, S * 8, ctx->stream) != hipSuccess ||
+    if (hipMemsetAsync(ctx->d_uid, 0, SP * 8, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_src, 0, SP * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_dst, 0, SP * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_sq, 0, SP, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_ipos, 0, SP * 8, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_off, 0, N4 * 4, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_cnt, 0, N4 * 4, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_counts, 0, N4 * ctx->QM * 4, ctx->stream) != hipSuccess ||

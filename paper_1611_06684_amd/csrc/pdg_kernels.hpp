@@ -401,6 +401,165 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
 }
 
 // ---------------------------------------------------------------------------
+// a3 with 33 or more chains: a wave takes E consecutive edge slots for one
+// block of 64 chains.  The slot metadata of all E edges comes in one batch of
+// scalar loads and their endpoint states in one batch of gathers; the
+// parameter block of the next edge is requested while the current edge is
+// drawn, and the mask words of all E edges are stored at the end, so every
+// load precedes every store.  Draws and mask logic are those of k_dual.
+// The slot arrays are padded to a multiple of E; free slots have uid 0.
+// ---------------------------------------------------------------------------
+constexpr int kDualEdgesPerWave = 4;
+
+template <int QM>
+struct DualParams {
+    uint64_t sign;
+    uint32_t thr[2 * dim_d(QM)];
+};
+
+template <int QM, bool UQ, int E>
+__global__ __launch_bounds__(256) void k_dual64(Graph g, uint32_t t)
+{
+    constexpr int D = dim_d(QM);
+    constexpr int NCALL = (D + 4) / 5;
+    constexpr int NW = 2 * D;  // mask half-words of one edge
+    constexpr int NREG = (NW + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t group = (g.CB == 1) ? wave : wave / g.CB;
+    const int cb = (int)(wave - group * g.CB);
+    const int c = cb * 64 + lane;
+    const bool cvalid = c < g.C;
+    const int64_t s0 = group * E;
+    if (s0 >= g.hwm) return;
+    uint64_t uid[E];
+    int32_t sv[E], dv[E];
+    uint32_t r0[E], r1[E], sq[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        uid[e] = g.uid[s0 + e];
+        sv[e] = g.src[s0 + e];
+        dv[e] = g.dst[s0 + e];
+        r0[e] = g.ipos[2 * (s0 + e)];
+        r1[e] = g.ipos[2 * (s0 + e) + 1];
+        sq[e] = UQ ? 0u : (uint32_t)g.sq[s0 + e];
+    }
+    // endpoint states, loaded unconditionally (free slots hold valid stale
+    // endpoints, or 0; lanes past C read chain 0 and their bits are masked)
+    const int cx = cvalid ? c : 0;
+    int xs[E], xd[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        xs[e] = g.x[(int64_t)sv[e] * g.C + cx];
+        xd[e] = g.x[(int64_t)dv[e] * g.C + cx];
+    }
+    const uint64_t mact = __ballot(cvalid);
+    auto load_params = [&](int64_t slot, DualParams<QM> &p) {
+        const uint8_t *blk = g.params + slot * block_bytes(QM);
+        p.sign = *reinterpret_cast<const uint64_t *>(blk);
+        const uint32_t *thr = reinterpret_cast<const uint32_t *>(blk + off_thr(QM));
+#pragma unroll
+        for (int i = 0; i < 2 * D; ++i) p.thr[i] = thr[i];
+    };
+    // touch the E parameter blocks (contiguous) with vector loads, all lines
+    // in flight at once, so the scalar loads of the edge loop hit L2
+    uint32_t sink;
+    {
+        constexpr int64_t BB = block_bytes(QM);
+        const uint64_t pb = (uint64_t)s0 * BB, pe = pb + (uint64_t)E * BB;
+        const uint64_t pa = (pb & ~(uint64_t)127) + 128 * (uint64_t)lane;
+        sink = pa < pe ? *reinterpret_cast<const uint32_t *>(g.params + pa) : 0u;
+    }
+    // and the record indices, which the stores at the end read
+    const uint32_t sink_ip = lane == 63 ? g.ipos[2 * s0] : 0u;
+    uint32_t outr[E][NREG];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+#pragma unroll
+        for (int r = 0; r < NREG; ++r) outr[e][r] = 0u;
+        if (uid[e] != 0) {
+            DualParams<QM> cur;
+            load_params(s0 + e, cur);
+            int qs = QM, qd = QM;
+            if (!UQ) {
+                qs = (int)(sq[e] & 15u);
+                qd = (int)(sq[e] >> 4);
+            }
+            const int De = UQ ? D : (qs - 1) * (qd - 1);
+            const uint32_t ulo = (uint32_t)uid[e], uhi = (uint32_t)(uid[e] >> 32);
+            uint64_t mya[QM], myb[QM];
+#pragma unroll
+            for (int v = 1; v < QM; ++v) {
+                mya[v] = __ballot(xs[e] == v);
+                myb[v] = __ballot(xd[e] == v);
+            }
+            int an = 1, bn = 1;  // entry (a, b) of the next draw when not UQ
+#pragma unroll
+            for (int k = 0; k < NCALL; ++k) {
+                if (!UQ && 5 * k >= De) break;
+                const Words w = philox4x32_10(ulo, uhi, (kPhaseDual << 30) | (uint32_t)(16 * c + k),
+                                              t, g.rk);
+                const uint32_t W[5] = {w.w0, w.w1, w.w2, w.w3,
+                                       (w.w0 << 24) | ((w.w1 & 0xFFu) << 16) |
+                                           ((w.w2 & 0xFFu) << 8)};
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    const int dd = 5 * k + j;
+                    if (dd >= D) break;
+                    int ai = an, bi = bn;  // 1-based entry (a, b) of draw dd
+                    if (UQ) {
+                        ai = dd / (QM - 1) + 1;
+                        bi = dd % (QM - 1) + 1;
+                    } else if (++bn == qd) {
+                        bn = 1;
+                        ++an;
+                    }
+                    uint64_t ya = 0, yb = 0;
+#pragma unroll
+                    for (int v = 1; v < QM; ++v) {
+                        if (v == ai) ya = mya[v];
+                        if (v == bi) yb = myb[v];
+                    }
+                    const uint64_t neg = 0ull - ((cur.sign >> dd) & 1ull);
+                    const uint64_t yh = ya ^ neg;
+                    const uint64_t cp = __ballot(W[j] > cur.thr[2 * dd]);        // U >= T+
+                    const uint64_t cm = __ballot(W[j] >= cur.thr[2 * dd + 1]);   // U >= T-
+                    const uint64_t ch = __ballot(W[j] >= 0x80000000u);          // U >= 2^23
+                    uint64_t zm = cp | (ch & (yh | yb)) | (cm & yh & yb);
+                    zm &= mact;
+                    if (!UQ && dd >= De) zm = 0;
+                    outr[e][(2 * dd) >> 6] =
+                        pdg_writelane_i32((uint32_t)zm, (2 * dd) & 63, outr[e][(2 * dd) >> 6]);
+                    outr[e][(2 * dd + 1) >> 6] = pdg_writelane_i32(
+                        (uint32_t)(zm >> 32), (2 * dd + 1) & 63, outr[e][(2 * dd + 1) >> 6]);
+                }
+            }
+        }
+    }
+    asm volatile("" ::"v"(sink), "v"(sink_ip));
+    // lane 2d + h holds half h of entry d's mask; the src record takes entry
+    // (a-1)(QM-1) + (b-1), the dst record (b-1)(QM-1) + (a-1)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int qd = UQ ? QM : (int)(sq[e] >> 4);
+        const int De = UQ ? D : ((int)(sq[e] & 15u) - 1) * (qd - 1);
+        uint32_t *z0 = g.rec_z + ((uint64_t)r0[e] * g.CB + cb) * 2 * D;
+        uint32_t *z1 = g.rec_z + ((uint64_t)r1[e] * g.CB + cb) * 2 * D;
+#pragma unroll
+        for (int r = 0; r < NREG; ++r) {
+            const int idx = 64 * r + lane;
+            const int dd = idx >> 1;
+            if (uid[e] != 0 && idx < NW && dd < De) {
+                const int ai = dd / (qd - 1), bi = dd % (qd - 1);
+                z0[2 * (ai * (QM - 1) + bi) + (idx & 1)] = outr[e][r];
+                z1[2 * (bi * (QM - 1) + ai) + (idx & 1)] = outr[e][r];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // a4 + a5: primal phase and marginal counting.  Lane (node quad Q, chain c)
 // takes one generator call (Q, PRIMAL, c, t) and walks the quad's four nodes;
 // node 4Q + j draws with word j.  For node i:
