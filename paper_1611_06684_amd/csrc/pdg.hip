@@ -58,6 +58,7 @@ struct pdg_ctx {
     double *d_lam = nullptr;
     uint8_t *d_x = nullptr;
     uint32_t *d_counts = nullptr;
+    double *d_base = nullptr;  // [n][QM] lam + c0 of the node's incidences
     int32_t *d_src = nullptr, *d_dst = nullptr;
     uint64_t *d_uid = nullptr;
     uint8_t *d_sq = nullptr;
@@ -172,6 +173,7 @@ static Graph make_graph(pdg_ctx *ctx)
     g.sq = ctx->d_sq;
     g.params = ctx->d_params;
     g.ipos = ctx->d_ipos;
+    g.base = ctx->d_base;
     g.inc_off = ctx->d_off;
     g.inc_cnt = ctx->d_cnt;
     g.inc = ctx->d_pool;
@@ -209,7 +211,10 @@ static void launch_primal_t(const Graph &g, uint32_t t, int count, int CB, hipSt
 {
     constexpr int P = 64 / LPI;
     const int64_t waves = cdiv(cdiv(g.n, 4), P) * CB;
-    k_primal<QM, LPI, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
+    if constexpr (LPI == 64)
+        k_primal64<QM, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
+    else
+        k_primal<QM, LPI, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
 }
 
 template <int QM, bool UQ>
@@ -495,14 +500,15 @@ static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &t
         double *nrp = nullptr;
         uint32_t *nrz = nullptr;
         PDG_TRY(dalloc(ctx, (void **)&npool, cap * 4));
-        pdg_status a = dalloc(ctx, (void **)&nrp, cap * ctx->RP * 8);
+        // the primal stages records in 16-byte pieces: pad past the last one
+        pdg_status a = dalloc(ctx, (void **)&nrp, cap * ctx->RP * 8 + 256);
         if (a == PDG_OK) a = dalloc(ctx, (void **)&nrz, cap * ctx->ZW * 4);
         if (a != PDG_OK) {
             (void)hipFree(npool);
             if (nrp) (void)hipFree(nrp);
             return a;
         }
-        PDG_HIP(ctx, hipMemsetAsync(nrp, 0, cap * ctx->RP * 8, ctx->stream));
+        PDG_HIP(ctx, hipMemsetAsync(nrp, 0, cap * ctx->RP * 8 + 256, ctx->stream));
         PDG_HIP(ctx, hipMemsetAsync(nrz, 0, cap * ctx->ZW * 4, ctx->stream));
         if (nmv && ctx->d_rec_p) {
             k_move_rec_p<<<grid_for(nmv * ctx->RP), 256, 0, ctx->stream>>>(nmv, ctx->RP, dmf, dmt,
@@ -553,7 +559,7 @@ static void free_all(pdg_ctx *ctx)
     void *ps[] = {ctx->d_q,     ctx->d_lam,   ctx->d_x,     ctx->d_counts, ctx->d_src,
                   ctx->d_dst,   ctx->d_uid,   ctx->d_sq,    ctx->d_params, ctx->d_ipos,
                   ctx->d_off,   ctx->d_cnt,   ctx->d_pool,  ctx->d_rec_p,  ctx->d_rec_z,
-                  ctx->d_flag,  ctx->d_scratch};
+                  ctx->d_flag,  ctx->d_scratch, ctx->d_base};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -617,6 +623,7 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
         (s = dalloc(ctx, (void **)&ctx->d_lam, N * ctx->QM * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_x, N * ctx->C)) ||
         (s = dalloc(ctx, (void **)&ctx->d_counts, N4 * ctx->QM * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_base, N4 * ctx->QM * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_src, SP * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_dst, SP * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_uid, SP * 8)) ||
@@ -635,6 +642,7 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
         hipMemsetAsync(ctx->d_off, 0, N4 * 4, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_cnt, 0, N4 * 4, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_counts, 0, N4 * ctx->QM * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_base, 0, N4 * ctx->QM * 8, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_x, 0, N * ctx->C, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)
         return bail(fail(ctx, PDG_EHIP, "initial clear failed"));
@@ -701,6 +709,9 @@ pdg_status pdg_set_nodes(pdg_ctx *ctx, int64_t n, const int32_t *d_q, const void
     ctx->n = n;
     PDG_HIP(ctx, hipMemsetAsync(ctx->d_off, 0, n * 4, ctx->stream));
     PDG_HIP(ctx, hipMemsetAsync(ctx->d_cnt, 0, n * 4, ctx->stream));
+    // no incidences yet: base = lam
+    PDG_HIP(ctx, hipMemcpyAsync(ctx->d_base, ctx->d_lam, n * ctx->QM * 8, hipMemcpyDeviceToDevice,
+                                ctx->stream));
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->nodes_set = true;
     return PDG_OK;
@@ -787,10 +798,14 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     // device: incidence structure and records (moves, ipos), then slot
     // arrays, decomposition of the new tables, and their records
     PDG_TRY(upload(ctx, P, touched));
+    const int64_t nn = (int64_t)touched.size();
+    std::vector<uint32_t> hnodes(touched.begin(), touched.end());
     void *s;
-    PDG_TRY(scratch(ctx, 8 * m + 4 * m * 3 + 64, &s));
+    PDG_TRY(scratch(ctx, 8 * m + 4 * m * 3 + 4 * nn + 64, &s));
     uint64_t *du = (uint64_t *)s;
     int32_t *dslot = (int32_t *)(du + m), *dqs = dslot + m, *dqd = dqs + m;
+    uint32_t *dnodes = (uint32_t *)(dqd + m);
+    PDG_HIP(ctx, hipMemcpyAsync(dnodes, hnodes.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
     PDG_HIP(ctx, hipMemcpyAsync(du, uids.data(), m * 8, hipMemcpyHostToDevice, ctx->stream));
     PDG_HIP(ctx, hipMemcpyAsync(dslot, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
     k_slot_write<<<grid_for(m), 256, 0, ctx->stream>>>(m, dslot, d_src, d_dst, du, ctx->d_q,
@@ -803,6 +818,9 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     PDG_HIP(ctx, hipGetLastError());
     k_write_records<<<grid_for(m * ctx->RP), 256, 0, ctx->stream>>>(
         m, ctx->QM, dslot, ctx->d_sq, ctx->d_params, ctx->d_ipos, ctx->d_rec_p);
+    k_node_base<<<grid_for(nn * ctx->QM), 256, 0, ctx->stream>>>(
+        nn, ctx->QM, dnodes, ctx->d_lam, ctx->d_off, ctx->d_cnt, ctx->d_pool, ctx->d_params,
+        ctx->d_base);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PDG_OK;
@@ -833,8 +851,9 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
     }
     Patches P;
     std::vector<int64_t> touched;
-    std::vector<uint32_t> recs;
+    std::vector<uint32_t> recs, hnodes;
     recs.reserve(2 * m);
+    hnodes.reserve(2 * m);
     for (int64_t k = 0; k < m; ++k) {
         const int32_t s = slots[k];
         const int32_t a = st.src[s], b = st.dst[s];
@@ -847,21 +866,31 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
         P.val.push_back(kTomb);
         recs.push_back(ia);
         recs.push_back(ib);
+        hnodes.push_back((uint32_t)a);
+        hnodes.push_back((uint32_t)b);
         st.nlive[a]--;
         st.nlive[b]--;
         st.free_stack.push_back(s);
     }
     st.live -= m;
     PDG_TRY(upload(ctx, P, touched));
+    std::sort(hnodes.begin(), hnodes.end());
+    hnodes.erase(std::unique(hnodes.begin(), hnodes.end()), hnodes.end());
+    const int64_t nn = (int64_t)hnodes.size();
     void *sp;
-    PDG_TRY(scratch(ctx, 4 * m + 8 * m + 512, &sp));
+    PDG_TRY(scratch(ctx, 4 * m + 8 * m + 4 * nn + 768, &sp));
     int32_t *dsl = (int32_t *)sp;
     uint32_t *drec = (uint32_t *)((char *)sp + ((4 * m + 255) / 256) * 256);
+    uint32_t *dnodes = (uint32_t *)((char *)drec + ((8 * m + 255) / 256) * 256);
     PDG_HIP(ctx, hipMemcpyAsync(dsl, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
     PDG_HIP(ctx, hipMemcpyAsync(drec, recs.data(), 2 * m * 4, hipMemcpyHostToDevice, ctx->stream));
+    PDG_HIP(ctx, hipMemcpyAsync(dnodes, hnodes.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
     k_slot_clear<<<grid_for(m), 256, 0, ctx->stream>>>(m, dsl, ctx->d_uid);
     k_clear_records<<<grid_for(2 * m * ctx->RP), 256, 0, ctx->stream>>>(2 * m, ctx->RP, drec,
                                                                        ctx->d_rec_p);
+    k_node_base<<<grid_for(nn * ctx->QM), 256, 0, ctx->stream>>>(
+        nn, ctx->QM, dnodes, ctx->d_lam, ctx->d_off, ctx->d_cnt, ctx->d_pool, ctx->d_params,
+        ctx->d_base);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PDG_OK;

@@ -14,12 +14,14 @@
 //   inc     uint32 pool                   per-node incidence segments
 //                                         [off, off + cnt): slot << 1 | side
 //                                         (side 0: node is src), or kTomb
-//   rec_p   double [pool][RP]             incidence records, RP = D + QM - 1,
-//                                         in the node's orientation: entry
-//                                         (r-1)(QM-1) + (o-1) for own state r,
-//                                         other end's state o (h on the src
-//                                         side, |h| on the dst side), then the
-//                                         side's c0; zero for tombstones
+//   rec_p   double [pool][D]              incidence records in the node's
+//                                         orientation: entry (r-1)(QM-1) + (o-1)
+//                                         for own state r, other end's state o
+//                                         (h on the src side, |h| on the dst
+//                                         side); zero for tombstones
+//   base    double [n][QM]                lam plus the theta-free part c0 of
+//                                         every incidence of the node, summed
+//                                         in record order
 //   rec_z   words  [pool][CB][D]          dual masks of each incidence record,
 //                                         same entry order: with C <= 32 a
 //                                         32-bit word per (record, entry), bit
@@ -59,6 +61,7 @@ __host__ __device__ constexpr int64_t block_bytes(int qm)
 struct Graph {
     const uint8_t *__restrict__ q;        // [n] states per node
     const double *__restrict__ lam;       // [n][QM] log unaries (FP64)
+    const double *__restrict__ base;      // [n][QM] lam + the c0 of the node's records
     const int32_t *__restrict__ src;      // [slots]
     const int32_t *__restrict__ dst;      // [slots]
     const uint64_t *__restrict__ uid;     // [slots], 0 = free slot
@@ -80,7 +83,7 @@ struct Graph {
     RoundKeys rk;                         // its ten round keys
 };
 
-__host__ __device__ constexpr int rec_len(int qm) { return dim_d(qm) + qm - 1; }
+__host__ __device__ constexpr int rec_len(int qm) { return dim_d(qm); }
 // u32 words of dual masks per incidence record
 __host__ __device__ inline int64_t rec_words(int qm, int C)
 {
@@ -559,6 +562,208 @@ __global__ __launch_bounds__(256) void k_dual64(Graph g, uint32_t t)
     }
 }
 
+// Categorical draw of one node from its field L (FP64): m = max L, weights
+// e^(L(a) - m) (FP32 exp unless EXP64), F cumulative in FP64, x = min{a :
+// u F_{q-1} < F_a} with u = (U + 0.5) 2^-24.
+template <int QM, bool UQ, bool EXP64>
+__device__ __forceinline__ int draw_node(const double (&L)[QM], int qn, uint32_t U)
+{
+    double mx = L[0];
+#pragma unroll
+    for (int a = 1; a < QM; ++a)
+        if (UQ || a < qn) mx = fmax(mx, L[a]);
+    double F[QM];
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < QM; ++a) {
+        if (UQ || a < qn) {
+            double wgt;
+            if (EXP64)
+                wgt = exp(L[a] - mx);
+            else
+                wgt = (double)exp2f((float)((L[a] - mx) * 1.4426950408889634074));
+            acc += wgt;
+        }
+        F[a] = acc;
+    }
+    const double target = ((double)U + 0.5) * 5.9604644775390625e-08 * F[QM - 1];
+    int xn = qn - 1;
+#pragma unroll
+    for (int a = QM - 1; a >= 0; --a)
+        if ((UQ || a < qn) && target < F[a]) xn = a;
+    return xn;
+}
+
+// ---------------------------------------------------------------------------
+// a4 + a5 with 33 or more chains: a wave takes one node quad for one block of
+// 64 chains.  The h values of the quad's records are staged into the wave's
+// LDS region with one batch of 16-byte vector loads (all four nodes in flight
+// together) and read back as broadcasts; the dual masks, which are lane masks
+// used directly as FMA selects, come through scalar loads, two records per
+// wait, after their lines were touched into L2.  A node with more records
+// than a staged chunk holds is walked chunk by chunk.
+// ---------------------------------------------------------------------------
+template <int QM, bool UQ, bool EXP64>
+__global__ __launch_bounds__(256) void k_primal64(Graph g, uint32_t t, int count)
+{
+    constexpr int D = dim_d(QM);
+    constexpr int RP = rec_len(QM);                         // doubles per record
+    constexpr int NLD = D <= 16 ? 1 : 2;                    // 16-byte loads per lane and node
+    constexpr int CHB = 1024 * NLD;                         // staged bytes per node
+    constexpr int K = (CHB - 16) / (8 * RP);                // records per chunk
+    static_assert(K >= 1, "chunk holds no record");
+    __shared__ __align__(16) uint8_t stage[4][4][CHB];      // [wave of block][node][bytes]
+    const LaneMap<64> lm(g.C);
+    const int lane = lm.lane;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t quad = lm.item;
+    const bool cvalid = lm.c < g.C;
+    uint32_t off[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+    if (quad * 4 < g.n) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            off[j] = g.inc_off[quad * 4 + j];
+            cnt[j] = g.inc_cnt[quad * 4 + j];
+        }
+    }
+    // records [first, first + nrec) of node j into its LDS region; returns the
+    // byte shift of the first record (the copy starts 16-byte aligned; the
+    // record array is padded past its end)
+    auto stage_chunk = [&](int j, uint32_t first, uint32_t nrec) -> uint32_t {
+        const uint64_t start = ((uint64_t)off[j] + first) * (RP * 8);
+        const uint64_t a16 = start & ~(uint64_t)15;
+        const uint32_t shift = (uint32_t)(start - a16);
+        const uint32_t bytes = shift + nrec * (RP * 8);
+        const uint8_t *src = reinterpret_cast<const uint8_t *>(g.rec_p) + a16;
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
+            if (o < bytes)
+                *reinterpret_cast<uint4 *>(&stage[wib][j][o]) =
+                    *reinterpret_cast<const uint4 *>(src + o);
+        }
+        return shift;
+    };
+    uint32_t shift[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) shift[j] = stage_chunk(j, 0, cnt[j] < K ? cnt[j] : K);
+    // mask lines of the four segments into L2 (lane (j, l): line l of node j)
+    const int64_t zstride = (int64_t)g.CB * D * 2;  // u32 per record
+    uint32_t sink_z = 0;
+    {
+        const int j = lane >> 4, l = lane & 15;
+        const uint32_t oj = j == 0 ? off[0] : j == 1 ? off[1] : j == 2 ? off[2] : off[3];
+        const uint32_t cj = j == 0 ? cnt[0] : j == 1 ? cnt[1] : j == 2 ? cnt[2] : cnt[3];
+        const uint64_t zb = (uint64_t)oj * zstride * 4, ze = zb + (uint64_t)cj * zstride * 4;
+        const uint64_t za = (zb & ~(uint64_t)127) + 128 * (uint64_t)l;
+        if (za < ze)
+            sink_z = *reinterpret_cast<const uint32_t *>(
+                reinterpret_cast<const uint8_t *>(g.rec_z) + za);
+    }
+    // and the quad's base and counter rows (read later through scalar loads)
+    uint32_t sink_b = 0;
+    if (quad * 4 < g.n) {
+        // lanes 0..31: lines of the 32 QM base bytes; lanes 32..63: of the 16 QM counter bytes
+        const bool cpart = lane >= 32;
+        const uint64_t b0 = cpart ? (uint64_t)(g.counts + quad * 4 * QM) : (uint64_t)(g.base + quad * 4 * QM);
+        const uint64_t b1 = b0 + (cpart ? 16 * QM : 32 * QM);
+        const uint64_t ba = (b0 & ~(uint64_t)127) + 128 * (uint64_t)(lane & 31);
+        if (ba < b1 && (count || !cpart)) sink_b = *reinterpret_cast<const uint32_t *>(ba);
+    }
+    const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                   (kPhasePrimal << 30) | (uint32_t)lm.c, t, g.rk);
+    const uint32_t Wn[4] = {wq.w0, wq.w1, wq.w2, wq.w3};
+    int newx[4], qnv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t node = quad * 4 + j;
+        newx[j] = -1;
+        qnv[j] = 0;
+        if (node >= g.n) continue;
+        const int qn = UQ ? QM : (int)g.q[node];
+        qnv[j] = qn;
+        // the theta-free part (lam and every c0) is the node's base
+        double L[QM];
+#pragma unroll
+        for (int a = 0; a < QM; ++a) L[a] = (UQ || a < qn) ? g.base[node * QM + a] : 0.0;
+        auto record = [&](const double *h, const uint64_t *z) {
+#pragma unroll
+            for (int s = 1; s < QM; ++s) {
+                if (!UQ && s >= qn) break;
+                double acc = L[s];
+#pragma unroll
+                for (int o = 1; o < QM; ++o) {
+                    // acc + 2 theta h in one FMA: the factor is 0.0 or 2.0 (a
+                    // select of inline constants) and 2 h is exact
+                    const int dp = (s - 1) * (QM - 1) + (o - 1);
+                    const double zf = __hiloint2double(lane_bit(z[dp]) ? 0x40000000 : 0, 0);
+                    acc = __builtin_fma(zf, h[dp], acc);
+                }
+                L[s] = acc;
+            }
+        };
+        for (uint32_t first = 0; first < cnt[j]; first += K) {
+            const uint32_t nrec = (cnt[j] - first) < (uint32_t)K ? cnt[j] - first : (uint32_t)K;
+            const uint32_t sh = first == 0 ? shift[j] : stage_chunk(j, first, nrec);
+            const double *hs = reinterpret_cast<const double *>(&stage[wib][j][sh]);
+            const uint64_t *zq = reinterpret_cast<const uint64_t *>(
+                g.rec_z + ((uint64_t)off[j] + first) * zstride + (uint64_t)lm.cb * D * 2);
+            uint32_t k = 0;
+            // two records per step: their scalar mask loads share one wait
+            for (; k + 1 < nrec; k += 2) {
+                record(hs + k * RP, zq + (uint64_t)k * (zstride / 2));
+                record(hs + (k + 1) * RP, zq + (uint64_t)(k + 1) * (zstride / 2));
+            }
+            if (k < nrec) record(hs + k * RP, zq + (uint64_t)k * (zstride / 2));
+        }
+        newx[j] = draw_node<QM, UQ, EXP64>(L, qn, Wn[j] >> 8);
+    }
+    // the touch loads end here (their values are not used)
+    asm volatile("" ::"v"(sink_z), "v"(sink_b));
+    if (count && g.CB == 1) {
+        // The wave owns the quad's counters (the array is padded to whole
+        // quads): scalar-load them before any store, then store each node's
+        // row with one vector store (lane a holds state a).
+        uint32_t row[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool nvalid = quad * 4 + j < g.n;
+            row[j] = 0u;
+#pragma unroll
+            for (int a = 0; a < QM; ++a) {
+                const uint32_t v = g.counts[(quad * 4 + j) * QM + a] +
+                                   (uint32_t)__popcll(__ballot(nvalid && cvalid && newx[j] == a));
+                if (lane == a) row[j] = v;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t node = quad * 4 + j;
+            if (node < g.n && cvalid) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t node = quad * 4 + j;
+            if (node < g.n && lane < qnv[j]) g.counts[node * QM + lane] = row[j];
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t node = quad * 4 + j;
+        const bool nvalid = node < g.n;
+        if (nvalid && cvalid) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
+        if (count) {
+#pragma unroll
+            for (int a = 0; a < QM; ++a) {
+                const uint64_t bal = __ballot(nvalid && cvalid && newx[j] == a);
+                if (nvalid && lane == 0 && a < qnv[j] && bal != 0)
+                    atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(bal));
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a4 + a5: primal phase and marginal counting.  Lane (node quad Q, chain c)
 // takes one generator call (Q, PRIMAL, c, t) and walks the quad's four nodes;
@@ -623,38 +828,34 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
         if (nvalid) {
             int &qn = qnv[j];
             qn = UQ ? QM : (int)g.q[node];
+            // the theta-free part (lam and every c0) is the node's base
             double L[QM];
 #pragma unroll
-            for (int a = 0; a < QM; ++a) L[a] = 0.0;
+            for (int a = 0; a < QM; ++a) L[a] = (UQ || a < qn) ? g.base[node * QM + a] : 0.0;
             const double *hp = g.rec_p + (uint64_t)off[j] * RP;
             const uint32_t *zp = g.rec_z + (uint64_t)off[j] * zstride +
                                  ((LPI == 64) ? (uint64_t)lm.cb * D * 2 : 0);
-            for (uint32_t k = 0; k < cnt[j]; ++k, hp += RP, zp += zstride) {
-                const double *c0 = hp + D;
+            auto record = [&](const double *h, const uint32_t *z) {
                 auto theta = [&](int dp) -> bool {
-                    if (LPI == 64)
-                        return lane_bit(reinterpret_cast<const uint64_t *>(zp)[dp]);
-                    return ((zp[dp] >> (lm.c & 31)) & 1u) != 0;
+                    if (LPI == 64) return lane_bit(reinterpret_cast<const uint64_t *>(z)[dp]);
+                    return ((z[dp] >> (lm.c & 31)) & 1u) != 0;
                 };
 #pragma unroll
                 for (int s = 1; s < QM; ++s) {
                     if (!UQ && s >= qn) break;
-                    double acc = L[s] + c0[s - 1];
+                    double acc = L[s];
 #pragma unroll
                     for (int o = 1; o < QM; ++o) {
                         // acc + 2 theta h in one FMA: the factor is 0.0 or 2.0
                         // (a select of inline constants) and 2 h is exact
                         const int dp = (s - 1) * (QM - 1) + (o - 1);
                         const double zf = __hiloint2double(theta(dp) ? 0x40000000 : 0, 0);
-                        acc = __builtin_fma(zf, hp[dp], acc);
+                        acc = __builtin_fma(zf, h[dp], acc);
                     }
                     L[s] = acc;
                 }
-            }
-            const double *lam = g.lam + node * QM;
-#pragma unroll
-            for (int a = 0; a < QM; ++a)
-                if (UQ || a < qn) L[a] += lam[a];
+            };
+            for (uint32_t k = 0; k < cnt[j]; ++k, hp += RP, zp += zstride) record(hp, zp);
             double mx = L[0];
 #pragma unroll
             for (int a = 1; a < QM; ++a)
@@ -840,14 +1041,14 @@ __global__ void k_get_duals(int64_t m, int32_t QM, Graph g, const int32_t *__res
     out[idx] = bits;
 }
 
-// New edges: copy h / c0 of the parameter block into both incidence records,
-// each in its node's orientation (|h| on the dst side).  One thread per
-// (edge, value).
+// New edges: copy h of the parameter block into both incidence records, each
+// in its node's orientation (|h| on the dst side).  One thread per (edge,
+// entry).
 __global__ void k_write_records(int64_t m, int32_t QM, const int32_t *__restrict__ slots,
                                 const uint8_t *__restrict__ sq, const uint8_t *__restrict__ params,
                                 const uint32_t *__restrict__ ipos, double *__restrict__ rec_p)
 {
-    const int RP = rec_len(QM), D = dim_d(QM);
+    const int RP = rec_len(QM);
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= m * RP) return;
     const int64_t k = idx / RP;
@@ -855,18 +1056,12 @@ __global__ void k_write_records(int64_t m, int32_t QM, const int32_t *__restrict
     const int64_t s = slots[k];
     const uint8_t *blk = params + s * block_bytes(QM);
     const double *h = reinterpret_cast<const double *>(blk + off_h(QM));
-    const double *c0 = reinterpret_cast<const double *>(blk + off_c0(QM));
     const int qs = (int)(sq[s] & 15u), qd = (int)(sq[s] >> 4);
     double vs = 0.0, vd = 0.0;
-    if (j < D) {
-        // src record: row j / (QM-1) is the src state; dst record: the dst state
-        const int r = j / (QM - 1) + 1, o = j % (QM - 1) + 1;
-        if (r < qs && o < qd) vs = h[(r - 1) * (qd - 1) + (o - 1)];
-        if (o < qs && r < qd) vd = fabs(h[(o - 1) * (qd - 1) + (r - 1)]);
-    } else {
-        vs = c0[j - D];
-        vd = c0[(QM - 1) + j - D];
-    }
+    // src record: row j / (QM-1) is the src state; dst record: the dst state
+    const int r = j / (QM - 1) + 1, o = j % (QM - 1) + 1;
+    if (r < qs && o < qd) vs = h[(r - 1) * (qd - 1) + (o - 1)];
+    if (o < qs && r < qd) vd = fabs(h[(o - 1) * (qd - 1) + (r - 1)]);
     rec_p[(uint64_t)ipos[2 * s] * RP + j] = vs;
     rec_p[(uint64_t)ipos[2 * s + 1] * RP + j] = vd;
 }
@@ -879,6 +1074,32 @@ __global__ void k_clear_records(int64_t m, int32_t RP, const uint32_t *__restric
     if (idx >= m * RP) return;
     const int64_t k = idx / RP;
     rec_p[(uint64_t)rec[k] * RP + (idx - k * RP)] = 0.0;
+}
+
+// base of the listed nodes: lam plus the c0 of each live incidence (from the
+// edge's parameter block, the node's side), in record order.  One thread per
+// (node, state).
+__global__ void k_node_base(int64_t nn, int32_t QM, const uint32_t *__restrict__ nodes,
+                            const double *__restrict__ lam, const uint32_t *__restrict__ off,
+                            const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ inc,
+                            const uint8_t *__restrict__ params, double *__restrict__ base)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nn * QM) return;
+    const int64_t k = idx / QM;
+    const int a = (int)(idx - k * QM);
+    const uint64_t i = nodes[k];
+    double acc = lam[i * QM + a];
+    if (a >= 1) {
+        const int64_t bb = block_bytes(QM), oc0 = off_c0(QM);
+        for (uint32_t r = 0; r < cnt[i]; ++r) {
+            const uint32_t e = inc[off[i] + r];
+            if (e == kTomb) continue;
+            const double *c0 = reinterpret_cast<const double *>(params + (int64_t)(e >> 1) * bb + oc0);
+            acc += c0[(e & 1u) * (QM - 1) + (a - 1)];
+        }
+    }
+    base[i * QM + a] = acc;
 }
 
 // Moved incidence entries: record from[k] -> to[k] (u64 and u32 granules).
