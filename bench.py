@@ -1,23 +1,30 @@
 """Benchmark of the primal-dual Gibbs sweep on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--workload plain-grid|dynamic-sparse]
 
-Workload (seeded, synthetic): the plain grid -- 1024 x 1024 open 4-neighbour
-grid, q = 4, log-tables N(0, 0.2) per edge, log-unaries N(0, 1), FP32 tables,
-64 independent chains, sampler seed 0.  A step is one full sweep: the dual
-phase over every edge and chain, then the primal phase over every node and
-chain (with marginal counting).  The metric is chain * (|V| + |E|) updates/s
-with every input resident in HBM.
+Workloads (seeded, synthetic; recipes in workloads.py):
+  plain-grid (default, the headline line): 1024 x 1024 open 4-neighbour grid,
+    q = 4, log-tables N(0, 0.2) per edge, log-unaries N(0, 1), FP32 tables, 64
+    independent chains, sampler seed 0.
+  dynamic-sparse: Chung-Lu power-law graph, 2^22 nodes, exponent 2.5, mean
+    degree 8, q = 8, log-tables N(0, 0.15), 32 chains; every 10 sweeps 1 % of the
+    live edges are removed and as many inserted (edit batches prepared on the
+    device before timing; the edits themselves are timed).
+A step is one full sweep: the dual phase over every edge and chain, then the
+primal phase over every node and chain (with marginal counting).  The metric is
+chain * (|V| + |E|) updates/s with every input resident in HBM.
 
-Prints one JSON line.  ``roofline`` describes the dominant kernel (the dual
-phase): it is bound by integer VALU work (Philox draws), so achieved and peak
-are VALU issue slots per second; ``cpu_baseline`` is the FP64 oracle timed on
-the host cores on one step of the same workload.
+Prints one JSON line.  ``roofline`` describes the dual-phase kernel: it is
+bound by integer VALU work (Philox draws), so achieved and peak are VALU issue
+slots per second; ``cpu_baseline`` is the FP64 oracle timed on the host cores
+on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -41,15 +48,19 @@ DRAW_SLOTS = PHILOX_SLOTS / 5.0 + 3.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--chains", type=int, default=64)
-    p.add_argument("--side", type=int, default=1024)
+    p.add_argument("--steps", type=int, default=None)
+    p.add_argument("--warmup", type=int, default=None)
+    p.add_argument("--workload", choices=["plain-grid", "dynamic-sparse"], default="plain-grid")
     p.add_argument("--no-cpu-baseline", action="store_true")
     return p.parse_args()
 
 
-def cpu_baseline(model, C, seed):
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(model, C, seed, what="1 sweep of the full workload"):
+    """The oracle, as it stands, on one sweep of `model` with C chains."""
     from oracle import oracle
     dec = oracle.decompose(model)
     uid = np.arange(1, model.m + 1, dtype=np.uint64)
@@ -59,37 +70,23 @@ def cpu_baseline(model, C, seed):
     dt = time.perf_counter() - t0
     return {"value": C * (model.n + model.m) / dt, "unit": "updates/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"1 sweep of the full workload, {C} chains, {dt:.2f} s wall"}
+            "sample": f"{what}, {C} chains, {dt:.2f} s wall"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler's "
-              "chains would shard across GPUs with no per-sweep communication, but no "
-              "multi-GPU run is part of this build.", file=sys.stderr)
-        sys.exit(2)
+def timed_sweeps(s, steps, stream, between=None):
+    """Times `steps` sweeps on `stream` with events around each phase; `between(k)`
+    runs before sweep k (edits)."""
     import torch
-    from paper_1611_06684_amd import workloads as W
-    from paper_1611_06684_amd.pdg import Sampler
-
-    side, C, seed = args.side, args.chains, 0
-    model = W.table_grid(side, side, 4, seed=0)
-    s = Sampler(model, C, seed=seed, burn_in=0)
-    s.init()
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        s.dual_phase()
-        s.primal_phase()
-    torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t_start.record(stream)
-    for k in range(args.steps):
+    for k in range(steps):
+        if between is not None:
+            between(k)
         ev[k][0].record(stream)
         s.dual_phase()
         ev[k][1].record(stream)
@@ -101,36 +98,137 @@ def main():
     total_ms = t_start.elapsed_time(t_end)
     dual_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
     primal_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
-    s.sync()
+    return total_ms, dual_ms, primal_ms, wall
 
+
+def run_plain(args):
+    import torch
+    from paper_1611_06684_amd import workloads as W
+    from paper_1611_06684_amd.pdg import Sampler
+    steps = 200 if args.steps is None else args.steps
+    warmup = 20 if args.warmup is None else args.warmup
+    side, C, seed = 1024, 64, 0
+    model = W.table_grid(side, side, 4, seed=0)
+    s = Sampler(model, C, seed=seed, burn_in=0)
+    s.init()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        s.dual_phase()
+        s.primal_phase()
+    total_ms, dual_ms, primal_ms, wall = timed_sweeps(s, steps, stream)
+    s.sync()
+    s.close()
     updates = C * (model.n + model.m)
-    value = updates * args.steps / (total_ms / 1e3)
     draws_per_launch = model.m * 9 * C
     achieved = draws_per_launch * DRAW_SLOTS / (dual_ms / 1e3)
     out = {
         "metric": "chain*(|V|+|E|) updates/s",
-        "value": value,
+        "value": updates * steps / (total_ms / 1e3),
         "unit": "updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": total_ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": total_ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"plain grid {side}x{side}, q=4, FP32 tables, {C} chains",
                    "nodes": model.n, "edges": model.m, "chains": C, "seed": seed,
                    "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
                      "unit": "VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": None, "kernel": "k_dual<4,64>",
+                     "traffic": None, "kernel": "k_dual64<4,true,4>",
                      "work_per_draw_slots": DRAW_SLOTS},
     }
-    s.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(model, C, seed)
+    return out
+
+
+def run_dynamic(args):
+    import torch
+    from paper_1611_06684_amd import workloads as W
+    from paper_1611_06684_amd import pdg
+    from paper_1611_06684_amd.pdg import Sampler
+    steps = 50 if args.steps is None else args.steps
+    warmup = 10 if args.warmup is None else args.warmup
+    n, q, C, seed, every = 1 << 22, 8, 32, 0, 10
+    log("building the Chung-Lu graph")
+    model = W.chung_lu(n, q, seed=0)
+    log(f"graph: {model.n} nodes, {model.m} edges; uploading and decomposing")
+    s = Sampler(model, C, seed=seed, burn_in=0, edge_capacity=model.m)
+    s.init()
+    live = s.uids.clone()
+    m_live = int(live.numel())
+    # edit batches for every churn point of warmup + timed sweeps, staged on the device
+    churn = W.Churn(n, q, model.meta["weights"], seed=1)
+    n_batches = (warmup + steps + every - 1) // every
+    batches = []
+    for _ in range(n_batches):
+        pos, bs, bd, bL = churn.next_batch(np.arange(m_live))
+        batches.append(tuple(torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+                             for a in (pos.astype(np.int64), bs, bd, bL)))
+    log(f"{n_batches} edit batches of {len(batches[0][0])} removals + insertions staged")
+    state = {"live": live, "b": 0}
+
+    def edit(k):
+        if k % every != 0:
+            return
+        pos, bs, bd, bL = batches[state["b"]]
+        state["b"] += 1
+        lv = state["live"]
+        u = lv[pos].contiguous()
+        pdg.pdg_remove_edges(s.ctx, u.numel(), u.data_ptr())
+        new = torch.zeros(bs.numel(), dtype=torch.int64, device="cuda")
+        pdg.pdg_insert_edges(s.ctx, bs.numel(), bs.data_ptr(), bd.data_ptr(), bL.data_ptr(),
+                             new.data_ptr())
+        keep = torch.ones(lv.numel(), dtype=torch.bool, device="cuda")
+        keep[pos] = False
+        state["live"] = torch.cat([lv[keep], new])
+
+    stream = torch.cuda.current_stream()
+    for k in range(warmup):
+        edit(k)
+        s.dual_phase()
+        s.primal_phase()
+    log("warm-up done")
+    total_ms, dual_ms, primal_ms, wall = timed_sweeps(
+        s, steps, stream, between=lambda k: edit(warmup + k))
+    s.sync()
+    s.close()
+    updates = C * (model.n + m_live)
+    draws_per_launch = m_live * 49 * C
+    achieved = draws_per_launch * DRAW_SLOTS / (dual_ms / 1e3)
+    out = {
+        "metric": "chain*(|V|+|E|) updates/s",
+        "value": updates * steps / (total_ms / 1e3),
+        "unit": "updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": total_ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"dynamic sparse: Chung-Lu 2^22 nodes, q=8, FP32 tables, {C} chains, "
+                               f"1% churn every {every} sweeps",
+                   "nodes": model.n, "edges": m_live, "chains": C, "seed": seed,
+                   "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall,
+                   "edit_batches_timed": sum(1 for k in range(steps) if (warmup + k) % every == 0)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
+                     "unit": "VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
+                     "traffic": None, "kernel": "k_dual<8,32,true>",
+                     "work_per_draw_slots": DRAW_SLOTS},
+    }
+    if not args.no_cpu_baseline:
+        small = W.chung_lu(1 << 18, q, seed=0)
+        out["cpu_baseline"] = cpu_baseline(
+            small, C, seed, f"1 sweep of the same recipe at 2^18 nodes ({small.m} edges)")
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler's "
+              "chains would shard across GPUs with no per-sweep communication, but no "
+              "multi-GPU run is part of this build.", file=sys.stderr)
+        sys.exit(2)
+    out = run_plain(args) if args.workload == "plain-grid" else run_dynamic(args)
     print(json.dumps(out), flush=True)
 
 

@@ -210,11 +210,16 @@ template <int QM, int LPI, bool UQ, bool E64>
 static void launch_primal_t(const Graph &g, uint32_t t, int count, int CB, hipStream_t s)
 {
     constexpr int P = 64 / LPI;
-    const int64_t waves = cdiv(cdiv(g.n, 4), P) * CB;
-    if constexpr (LPI == 64)
+    if constexpr (LPI == 64) {
+        const int64_t waves = cdiv(g.n, 4) * CB;
         k_primal64<QM, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
-    else
+    } else if constexpr (LPI == 32) {
+        const int64_t waves = cdiv(g.n, 4);  // one quad per wave, halves split the records
+        k_primal32<QM, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
+    } else {
+        const int64_t waves = cdiv(cdiv(g.n, 4), P) * CB;
         k_primal<QM, LPI, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
+    }
 }
 
 template <int QM, bool UQ>
@@ -502,14 +507,14 @@ static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &t
         PDG_TRY(dalloc(ctx, (void **)&npool, cap * 4));
         // the primal stages records in 16-byte pieces: pad past the last one
         pdg_status a = dalloc(ctx, (void **)&nrp, cap * ctx->RP * 8 + 256);
-        if (a == PDG_OK) a = dalloc(ctx, (void **)&nrz, cap * ctx->ZW * 4);
+        if (a == PDG_OK) a = dalloc(ctx, (void **)&nrz, cap * ctx->ZW * 4 + 256);
         if (a != PDG_OK) {
             (void)hipFree(npool);
             if (nrp) (void)hipFree(nrp);
             return a;
         }
         PDG_HIP(ctx, hipMemsetAsync(nrp, 0, cap * ctx->RP * 8 + 256, ctx->stream));
-        PDG_HIP(ctx, hipMemsetAsync(nrz, 0, cap * ctx->ZW * 4, ctx->stream));
+        PDG_HIP(ctx, hipMemsetAsync(nrz, 0, cap * ctx->ZW * 4 + 256, ctx->stream));
         if (nmv && ctx->d_rec_p) {
             k_move_rec_p<<<grid_for(nmv * ctx->RP), 256, 0, ctx->stream>>>(nmv, ctx->RP, dmf, dmt,
                                                                           ctx->d_rec_p, nrp);

@@ -765,6 +765,166 @@ __global__ __launch_bounds__(256) void k_primal64(Graph g, uint32_t t, int count
 }
 
 // ---------------------------------------------------------------------------
+// a4 + a5 with 17..32 chains: a wave takes one node quad; lane (p, c) is half
+// p of the wave and chain c.  The two halves walk alternate records of the
+// same node (record k + p of each pair) and add their partial fields with one
+// cross-half exchange before the draw, so all 64 lanes work although a record
+// only covers 32 chains.  A chunk of the node's records -- h values and the
+// 32-bit mask words -- is staged in the wave's LDS region with 16-byte vector
+// loads; the quad's record lines are touched into L2 at wave start.
+// ---------------------------------------------------------------------------
+template <int QM, bool UQ, bool EXP64>
+__global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count)
+{
+    constexpr int D = dim_d(QM);
+    constexpr int RP = rec_len(QM);
+    constexpr int SB = 4096;                                 // LDS bytes per wave
+    constexpr int ZB = (4 * D + 15) / 16 * 16;               // zero mask block
+    constexpr int K = (SB - ZB - 32) / (8 * RP + 4 * D);     // records per chunk
+    constexpr int NLD = SB / 1024;                           // 16-byte loads per lane, max
+    static_assert(K >= 2, "chunk too small");
+    constexpr int HB = (16 + 8 * RP * K + 15) / 16 * 16;     // h part of the region
+    __shared__ __align__(16) uint8_t stage[4][SB];
+    const int lane = threadIdx.x & 63;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t quad = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    const int p = lane >> 5, c = lane & 31;
+    const bool cvalid = c < g.C;
+    if (quad * 4 >= g.n) return;
+    uint32_t off[4], cnt[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        off[j] = g.inc_off[quad * 4 + j];
+        cnt[j] = g.inc_cnt[quad * 4 + j];
+    }
+    uint8_t *reg = stage[wib];
+    if (lane < ZB / 16) *reinterpret_cast<uint4 *>(reg + SB - ZB + 16 * lane) = make_uint4(0, 0, 0, 0);
+    // record lines of the quad into L2 (lane (j, l): lines l, l + 16, ... of node j)
+    uint32_t sink = 0;
+    {
+        const int j = lane >> 4, l = lane & 15;
+        const uint32_t oj = j == 0 ? off[0] : j == 1 ? off[1] : j == 2 ? off[2] : off[3];
+        const uint32_t cj = j == 0 ? cnt[0] : j == 1 ? cnt[1] : j == 2 ? cnt[2] : cnt[3];
+        const uint64_t pb = (uint64_t)oj * (RP * 8), pe = pb + (uint64_t)cj * (RP * 8);
+        const uint64_t zb = (uint64_t)oj * (D * 4), ze = zb + (uint64_t)cj * (D * 4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint64_t pa = (pb & ~(uint64_t)127) + 128 * (uint64_t)(l + 16 * r);
+            if (pa < pe) sink += *reinterpret_cast<const uint32_t *>(
+                                     reinterpret_cast<const uint8_t *>(g.rec_p) + pa);
+            const uint64_t za = (zb & ~(uint64_t)127) + 128 * (uint64_t)(l + 16 * r);
+            if (za < ze) sink += *reinterpret_cast<const uint32_t *>(
+                                     reinterpret_cast<const uint8_t *>(g.rec_z) + za);
+        }
+    }
+    // bytes [a, a + n) of `src` into the region at `dst` from a 16-byte aligned
+    // start; returns the shift of byte a (the record arrays are padded past
+    // their ends)
+    auto copy16 = [&](const uint8_t *src, uint64_t a, uint32_t n, uint32_t dst) -> uint32_t {
+        const uint64_t a16 = a & ~(uint64_t)15;
+        const uint32_t shift = (uint32_t)(a - a16);
+        const uint32_t bytes = shift + n;
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
+            if (o < bytes)
+                *reinterpret_cast<uint4 *>(reg + dst + o) =
+                    *reinterpret_cast<const uint4 *>(src + a16 + o);
+        }
+        return shift;
+    };
+    const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                   (kPhasePrimal << 30) | (uint32_t)c, t, g.rk);
+    const uint32_t Wn[4] = {wq.w0, wq.w1, wq.w2, wq.w3};
+    const uint32_t *zero = reinterpret_cast<const uint32_t *>(reg + SB - ZB);
+    const uint32_t rot = (uint32_t)(c + 2) & 31u;
+    int newx[4], qnv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t node = quad * 4 + j;
+        newx[j] = -1;
+        qnv[j] = 0;
+        if (node >= g.n) continue;
+        const int qn = UQ ? QM : (int)g.q[node];
+        qnv[j] = qn;
+        // half 0 starts from the node's base (lam and every c0), half 1 from 0
+        double L[QM];
+#pragma unroll
+        for (int a = 0; a < QM; ++a)
+            L[a] = (p == 0 && (UQ || a < qn)) ? g.base[node * QM + a] : 0.0;
+        for (uint32_t first = 0; first < cnt[j]; first += K) {
+            const uint32_t nrec = (cnt[j] - first) < (uint32_t)K ? cnt[j] - first : (uint32_t)K;
+            const uint64_t r0 = (uint64_t)off[j] + first;
+            const uint32_t sh = copy16(reinterpret_cast<const uint8_t *>(g.rec_p), r0 * (RP * 8),
+                                       nrec * (RP * 8), 0);
+            const uint32_t sz = copy16(reinterpret_cast<const uint8_t *>(g.rec_z), r0 * (D * 4),
+                                       nrec * (D * 4), HB);
+            const double *hs = reinterpret_cast<const double *>(reg + sh);
+            const uint32_t *zs = reinterpret_cast<const uint32_t *>(reg + HB + sz);
+            for (uint32_t k = 0; k < nrec; k += 2) {
+                // half p takes record k + p; past the end it reads record k's h
+                // with an all-zero mask, which adds nothing
+                const bool has = k + p < nrec;
+                const double *h = hs + (has ? k + p : k) * RP;
+                const uint32_t *z = has ? zs + (k + p) * D : zero;
+#pragma unroll
+                for (int s = 1; s < QM; ++s) {
+                    if (!UQ && s >= qn) break;
+                    double acc = L[s];
+#pragma unroll
+                    for (int o = 1; o < QM; ++o) {
+                        const int dp = (s - 1) * (QM - 1) + (o - 1);
+                        // rotating the word right by c + 2 puts chain c's bit at bit 30,
+                        // the one set bit of 2.0's high word
+                        const uint32_t hi = __builtin_amdgcn_alignbit(z[dp], z[dp], rot) & 0x40000000u;
+                        const double zf = __hiloint2double((int)hi, 0);
+                        acc = __builtin_fma(zf, h[dp], acc);
+                    }
+                    L[s] = acc;
+                }
+            }
+        }
+        // both halves end with the same sum (IEEE addition is commutative)
+#pragma unroll
+        for (int s = 1; s < QM; ++s) L[s] += __shfl_xor(L[s], 32);
+        newx[j] = draw_node<QM, UQ, EXP64>(L, qn, Wn[j] >> 8);
+    }
+    asm volatile("" ::"v"(sink));
+    const bool writer = p == 0 && cvalid;
+    if (count) {
+        // the wave owns the quad's counters (one chain block; padded to whole quads)
+        uint32_t row[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool nvalid = quad * 4 + j < g.n;
+            row[j] = 0u;
+#pragma unroll
+            for (int a = 0; a < QM; ++a) {
+                const uint32_t v = g.counts[(quad * 4 + j) * QM + a] +
+                                   (uint32_t)__popcll(__ballot(nvalid && writer && newx[j] == a));
+                if (lane == a) row[j] = v;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t node = quad * 4 + j;
+            if (node < g.n && writer) g.x[node * g.C + c] = (uint8_t)newx[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t node = quad * 4 + j;
+            if (node < g.n && lane < qnv[j]) g.counts[node * QM + lane] = row[j];
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t node = quad * 4 + j;
+        if (node < g.n && writer) g.x[node * g.C + c] = (uint8_t)newx[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // a4 + a5: primal phase and marginal counting.  Lane (node quad Q, chain c)
 // takes one generator call (Q, PRIMAL, c, t) and walks the quad's four nodes;
 // node 4Q + j draws with word j.  For node i:
