@@ -33,6 +33,7 @@ struct Store {
     std::vector<int32_t> free_stack;
     int64_t hwm = 0, live = 0;
     std::vector<uint32_t> off, cnt, cap, nlive;  // per node
+    std::vector<uint32_t> mark;                  // per node, zero between calls (edit scratch)
     std::vector<uint32_t> pool;
     int64_t pool_top = 0;
 };
@@ -559,6 +560,28 @@ static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &t
     return PDG_OK;
 }
 
+template <int QM>
+static void node_base_q(pdg_ctx *ctx, int64_t nn, const uint32_t *dnodes)
+{
+    k_node_base<QM><<<grid_for(nn * 64), 256, 0, ctx->stream>>>(
+        nn, dnodes, ctx->d_lam, ctx->d_off, ctx->d_cnt, ctx->d_pool, ctx->d_params, ctx->d_base);
+}
+
+// base of the listed nodes (after their incidence lists changed)
+static void launch_node_base(pdg_ctx *ctx, int64_t nn, const uint32_t *dnodes)
+{
+    if (nn == 0) return;
+    switch (ctx->QM) {
+    case 2: node_base_q<2>(ctx, nn, dnodes); break;
+    case 3: node_base_q<3>(ctx, nn, dnodes); break;
+    case 4: node_base_q<4>(ctx, nn, dnodes); break;
+    case 5: node_base_q<5>(ctx, nn, dnodes); break;
+    case 6: node_base_q<6>(ctx, nn, dnodes); break;
+    case 7: node_base_q<7>(ctx, nn, dnodes); break;
+    default: node_base_q<8>(ctx, nn, dnodes); break;
+    }
+}
+
 static void free_all(pdg_ctx *ctx)
 {
     void *ps[] = {ctx->d_q,     ctx->d_lam,   ctx->d_x,     ctx->d_counts, ctx->d_src,
@@ -711,6 +734,7 @@ pdg_status pdg_set_nodes(pdg_ctx *ctx, int64_t n, const int32_t *d_q, const void
     st.cnt.assign(n, 0);
     st.cap.assign(n, 0);
     st.nlive.assign(n, 0);
+    st.mark.assign(n, 0);
     ctx->n = n;
     PDG_HIP(ctx, hipMemsetAsync(ctx->d_off, 0, n * 4, ctx->stream));
     PDG_HIP(ctx, hipMemsetAsync(ctx->d_cnt, 0, n * 4, ctx->stream));
@@ -773,17 +797,23 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     st.live += m;
     // incidence: room first (relocation or full compaction), then appends in batch order
     Patches P;
-    std::vector<uint32_t> need;
+    std::vector<uint32_t> &need = st.mark;  // reset for the touched nodes before returning
     std::vector<int64_t> touched;
     try {
-        need.assign(ctx->n, 0);
+        touched.reserve(2 * m);
         for (int64_t k = 0; k < m; ++k) {
             if (need[hs[k]]++ == 0) touched.push_back(hs[k]);
             if (need[hd[k]]++ == 0) touched.push_back(hd[k]);
         }
     } catch (...) {
+        for (int64_t k = 0; k < m; ++k) need[hs[k]] = need[hd[k]] = 0;
         return fail(ctx, PDG_ENOMEM, "host allocation failed");
     }
+    struct Reset {
+        std::vector<uint32_t> &v;
+        const std::vector<int64_t> &idx;
+        ~Reset() { for (int64_t i : idx) v[i] = 0; }
+    } reset_need{need, touched};
     uint64_t room = 0;
     for (int64_t i : touched)
         if (st.cnt[i] + need[i] > st.cap[i]) {
@@ -823,9 +853,7 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     PDG_HIP(ctx, hipGetLastError());
     k_write_records<<<grid_for(m * ctx->RP), 256, 0, ctx->stream>>>(
         m, ctx->QM, dslot, ctx->d_sq, ctx->d_params, ctx->d_ipos, ctx->d_rec_p);
-    k_node_base<<<grid_for(nn * ctx->QM), 256, 0, ctx->stream>>>(
-        nn, ctx->QM, dnodes, ctx->d_lam, ctx->d_off, ctx->d_cnt, ctx->d_pool, ctx->d_params,
-        ctx->d_base);
+    launch_node_base(ctx, nn, dnodes);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PDG_OK;
@@ -879,8 +907,13 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
     }
     st.live -= m;
     PDG_TRY(upload(ctx, P, touched));
-    std::sort(hnodes.begin(), hnodes.end());
-    hnodes.erase(std::unique(hnodes.begin(), hnodes.end()), hnodes.end());
+    {  // distinct endpoints, first-seen order
+        size_t w = 0;
+        for (size_t k = 0; k < hnodes.size(); ++k)
+            if (st.mark[hnodes[k]]++ == 0) hnodes[w++] = hnodes[k];
+        hnodes.resize(w);
+        for (uint32_t i : hnodes) st.mark[i] = 0;
+    }
     const int64_t nn = (int64_t)hnodes.size();
     void *sp;
     PDG_TRY(scratch(ctx, 4 * m + 8 * m + 4 * nn + 768, &sp));
@@ -893,9 +926,7 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
     k_slot_clear<<<grid_for(m), 256, 0, ctx->stream>>>(m, dsl, ctx->d_uid);
     k_clear_records<<<grid_for(2 * m * ctx->RP), 256, 0, ctx->stream>>>(2 * m, ctx->RP, drec,
                                                                        ctx->d_rec_p);
-    k_node_base<<<grid_for(nn * ctx->QM), 256, 0, ctx->stream>>>(
-        nn, ctx->QM, dnodes, ctx->d_lam, ctx->d_off, ctx->d_cnt, ctx->d_pool, ctx->d_params,
-        ctx->d_base);
+    launch_node_base(ctx, nn, dnodes);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PDG_OK;

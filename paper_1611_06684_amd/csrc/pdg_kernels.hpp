@@ -1237,29 +1237,43 @@ __global__ void k_clear_records(int64_t m, int32_t RP, const uint32_t *__restric
 }
 
 // base of the listed nodes: lam plus the c0 of each live incidence (from the
-// edge's parameter block, the node's side), in record order.  One thread per
-// (node, state).
-__global__ void k_node_base(int64_t nn, int32_t QM, const uint32_t *__restrict__ nodes,
-                            const double *__restrict__ lam, const uint32_t *__restrict__ off,
-                            const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ inc,
-                            const uint8_t *__restrict__ params, double *__restrict__ base)
+// edge's parameter block, the node's side).  One wave per node: lane l sums
+// records l, l + 64, ... and the wave adds the lanes' sums in a fixed butterfly,
+// so the result depends only on the node's record list.
+template <int QM>
+__global__ __launch_bounds__(256) void k_node_base(int64_t nn, const uint32_t *__restrict__ nodes,
+                                                   const double *__restrict__ lam,
+                                                   const uint32_t *__restrict__ off,
+                                                   const uint32_t *__restrict__ cnt,
+                                                   const uint32_t *__restrict__ inc,
+                                                   const uint8_t *__restrict__ params,
+                                                   double *__restrict__ base)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nn * QM) return;
-    const int64_t k = idx / QM;
-    const int a = (int)(idx - k * QM);
+    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= nn) return;
     const uint64_t i = nodes[k];
-    double acc = lam[i * QM + a];
-    if (a >= 1) {
-        const int64_t bb = block_bytes(QM), oc0 = off_c0(QM);
-        for (uint32_t r = 0; r < cnt[i]; ++r) {
-            const uint32_t e = inc[off[i] + r];
-            if (e == kTomb) continue;
-            const double *c0 = reinterpret_cast<const double *>(params + (int64_t)(e >> 1) * bb + oc0);
-            acc += c0[(e & 1u) * (QM - 1) + (a - 1)];
-        }
+    double acc[QM];
+#pragma unroll
+    for (int a = 0; a < QM; ++a) acc[a] = 0.0;
+    const uint32_t o = off[i], n = cnt[i];
+    for (uint32_t r = lane; r < n; r += 64) {
+        const uint32_t e = inc[o + r];
+        if (e == kTomb) continue;
+        const double *c0 = reinterpret_cast<const double *>(
+            params + (int64_t)(e >> 1) * block_bytes(QM) + off_c0(QM));
+#pragma unroll
+        for (int a = 1; a < QM; ++a) acc[a] += c0[(e & 1u) * (QM - 1) + (a - 1)];
     }
-    base[i * QM + a] = acc;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+#pragma unroll
+        for (int a = 1; a < QM; ++a) acc[a] += __shfl_xor(acc[a], m);
+    double v = 0.0;
+#pragma unroll
+    for (int a = 1; a < QM; ++a)
+        if (lane == a) v = acc[a];
+    if (lane < QM) base[i * QM + lane] = lam[i * QM + lane] + v;
 }
 
 // Moved incidence entries: record from[k] -> to[k] (u64 and u32 granules).
