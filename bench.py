@@ -43,6 +43,10 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 PHILOX_SLOTS = 10 * (2 + 2)
 DRAW_SLOTS = PHILOX_SLOTS / 5.0 + 3.0
+# HBM bytes per launch of k_dual64<4,true,4> on the plain grid: FETCH_SIZE x 2 +
+# WRITE_SIZE x 1 (factors from a 1 GiB copy), profiles/plain_grid_sweep_kernels.txt.
+# Measured for the kernel as it stands; it must be re-measured when the kernel changes.
+DUAL_TRAFFIC_PLAIN = 1031.1e6
 
 
 def parse():
@@ -52,6 +56,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=None)
     p.add_argument("--workload", choices=["plain-grid", "dynamic-sparse"], default="plain-grid")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-mib", type=int, default=0,
+                   help="after the run, copy a buffer of this many MiB three times (a plain "
+                        "copy kernel of known size, to calibrate memory counters)")
     return p.parse_args()
 
 
@@ -134,7 +141,7 @@ def run_plain(args):
                    "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
                      "unit": "VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": None, "kernel": "k_dual64<4,true,4>",
+                     "traffic": DUAL_TRAFFIC_PLAIN, "kernel": "k_dual64<4,true,4>",
                      "work_per_draw_slots": DRAW_SLOTS},
     }
     if not args.no_cpu_baseline:
@@ -230,6 +237,14 @@ def main():
         sys.exit(2)
     out = run_plain(args) if args.workload == "plain-grid" else run_dynamic(args)
     print(json.dumps(out), flush=True)
+    if args.copy_mib > 0:
+        import torch
+        a = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_mib} MiB three times")
 
 
 if __name__ == "__main__":
