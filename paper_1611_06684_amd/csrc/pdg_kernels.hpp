@@ -563,8 +563,9 @@ __global__ __launch_bounds__(256) void k_dual64(Graph g, uint32_t t)
 }
 
 // Categorical draw of one node from its field L (FP64): m = max L, weights
-// e^(L(a) - m) (FP32 exp unless EXP64), F cumulative in FP64, x = min{a :
-// u F_{q-1} < F_a} with u = (U + 0.5) 2^-24.
+// e^(L(a) - m) (FP32 exp unless EXP64: the hardware's 2^x on (L(a) - m) log2 e,
+// whose relative error is about 1e-7; weights below 2^-126 may flush to 0), F
+// cumulative in FP64, x = min{a : u F_{q-1} < F_a} with u = (U + 0.5) 2^-24.
 template <int QM, bool UQ, bool EXP64>
 __device__ __forceinline__ int draw_node(const double (&L)[QM], int qn, uint32_t U)
 {
@@ -581,7 +582,7 @@ __device__ __forceinline__ int draw_node(const double (&L)[QM], int qn, uint32_t
             if (EXP64)
                 wgt = exp(L[a] - mx);
             else
-                wgt = (double)exp2f((float)((L[a] - mx) * 1.4426950408889634074));
+                wgt = (double)__builtin_amdgcn_exp2f((float)((L[a] - mx) * 1.4426950408889634074));
             acc += wgt;
         }
         F[a] = acc;
@@ -1029,7 +1030,7 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
                     if (EXP64)
                         wgt = exp(L[a] - mx);
                     else
-                        wgt = (double)exp2f((float)((L[a] - mx) * 1.4426950408889634074));
+                        wgt = (double)__builtin_amdgcn_exp2f((float)((L[a] - mx) * 1.4426950408889634074));
                     acc += wgt;
                 }
                 F[a] = acc;
