@@ -770,22 +770,25 @@ __global__ __launch_bounds__(256) void k_primal64(Graph g, uint32_t t, int count
 // p of the wave and chain c.  The two halves walk alternate records of the
 // same node (record k + p of each pair) and add their partial fields with one
 // cross-half exchange before the draw, so all 64 lanes work although a record
-// only covers 32 chains.  A chunk of the node's records -- h values and the
-// 32-bit mask words -- is staged in the wave's LDS region with 16-byte vector
-// loads; the quad's record lines are touched into L2 at wave start.
+// only covers 32 chains.  The quad's records are walked as one stream of
+// chunks (a chunk: up to K records of one node, their h values and 32-bit
+// mask words); the next chunk is loaded into registers while the current one
+// is read from the wave's LDS buffer, then written to the other buffer.
 // ---------------------------------------------------------------------------
 template <int QM, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count)
 {
     constexpr int D = dim_d(QM);
     constexpr int RP = rec_len(QM);
-    constexpr int SB = 4096;                                 // LDS bytes per wave
-    constexpr int ZB = (4 * D + 15) / 16 * 16;               // zero mask block
-    constexpr int K = (SB - ZB - 32) / (8 * RP + 4 * D);     // records per chunk
-    constexpr int NLD = SB / 1024;                           // 16-byte loads per lane, max
+    constexpr int BUF = 3072;                                 // LDS bytes per buffer (two per wave)
+    constexpr int ZB = (4 * D + 15) / 16 * 16;                // zero mask block (once per wave)
+    constexpr int K = (BUF - 32) / (8 * RP + 4 * D);          // records per chunk
     static_assert(K >= 2, "chunk too small");
-    constexpr int HB = (16 + 8 * RP * K + 15) / 16 * 16;     // h part of the region
-    __shared__ __align__(16) uint8_t stage[4][SB];
+    constexpr int HB = (16 + 8 * RP * K + 15) / 16 * 16;      // h part of a buffer
+    constexpr int NH = (HB + 1023) / 1024;                    // 16-byte loads per lane, h part
+    constexpr int NZ = (16 + 4 * D * K + 1023) / 1024;        // and mask part
+    static_assert(HB + 16 * 64 * NZ <= BUF + 16 * 64 * NZ, "layout");
+    __shared__ __align__(16) uint8_t lds[4][2 * BUF + ZB];
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t quad = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
@@ -796,132 +799,175 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         off[j] = g.inc_off[quad * 4 + j];
-        cnt[j] = g.inc_cnt[quad * 4 + j];
+        cnt[j] = quad * 4 + j < g.n ? g.inc_cnt[quad * 4 + j] : 0u;
     }
-    uint8_t *reg = stage[wib];
-    if (lane < ZB / 16) *reinterpret_cast<uint4 *>(reg + SB - ZB + 16 * lane) = make_uint4(0, 0, 0, 0);
-    // record lines of the quad into L2 (lane (j, l): lines l, l + 16, ... of node j)
-    uint32_t sink = 0;
-    {
-        const int j = lane >> 4, l = lane & 15;
-        const uint32_t oj = j == 0 ? off[0] : j == 1 ? off[1] : j == 2 ? off[2] : off[3];
-        const uint32_t cj = j == 0 ? cnt[0] : j == 1 ? cnt[1] : j == 2 ? cnt[2] : cnt[3];
-        const uint64_t pb = (uint64_t)oj * (RP * 8), pe = pb + (uint64_t)cj * (RP * 8);
-        const uint64_t zb = (uint64_t)oj * (D * 4), ze = zb + (uint64_t)cj * (D * 4);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint64_t pa = (pb & ~(uint64_t)127) + 128 * (uint64_t)(l + 16 * r);
-            if (pa < pe) sink += *reinterpret_cast<const uint32_t *>(
-                                     reinterpret_cast<const uint8_t *>(g.rec_p) + pa);
-            const uint64_t za = (zb & ~(uint64_t)127) + 128 * (uint64_t)(l + 16 * r);
-            if (za < ze) sink += *reinterpret_cast<const uint32_t *>(
-                                     reinterpret_cast<const uint8_t *>(g.rec_z) + za);
+    uint8_t *reg = lds[wib];
+    if (lane < ZB / 16)
+        *reinterpret_cast<uint4 *>(reg + 2 * BUF + 16 * lane) = make_uint4(0, 0, 0, 0);
+    const uint32_t *zero = reinterpret_cast<const uint32_t *>(reg + 2 * BUF);
+    const uint32_t rot = (uint32_t)(c + 2) & 31u;
+    // chunk cursor: node j, first record
+    auto sel = [&](const uint32_t (&a)[4], int j) -> uint32_t {
+        return j == 0 ? a[0] : j == 1 ? a[1] : j == 2 ? a[2] : a[3];
+    };
+    auto skip_empty = [&](int &j, uint32_t &first) {
+        while (j < 4 && first >= sel(cnt, j)) {
+            ++j;
+            first = 0;
         }
-    }
-    // bytes [a, a + n) of `src` into the region at `dst` from a 16-byte aligned
-    // start; returns the shift of byte a (the record arrays are padded past
-    // their ends)
-    auto copy16 = [&](const uint8_t *src, uint64_t a, uint32_t n, uint32_t dst) -> uint32_t {
-        const uint64_t a16 = a & ~(uint64_t)15;
-        const uint32_t shift = (uint32_t)(a - a16);
-        const uint32_t bytes = shift + n;
+    };
+    // registers of a chunk in flight
+    uint4 rh[NH], rz[NZ];
+    uint32_t sh_h = 0, sh_z = 0;  // byte shifts of its first record
+    auto issue = [&](int j, uint32_t first) {
+        const uint32_t nrec = min(sel(cnt, j) - first, (uint32_t)K);
+        const uint64_t r0 = (uint64_t)sel(off, j) + first;
+        const uint64_t ah = r0 * (RP * 8), az = r0 * (D * 4);
+        sh_h = (uint32_t)(ah & 15);
+        sh_z = (uint32_t)(az & 15);
+        const uint8_t *ph = reinterpret_cast<const uint8_t *>(g.rec_p) + (ah - sh_h);
+        const uint8_t *pz = reinterpret_cast<const uint8_t *>(g.rec_z) + (az - sh_z);
+        const uint32_t bh = sh_h + nrec * (RP * 8), bz = sh_z + nrec * (D * 4);
 #pragma unroll
-        for (int i = 0; i < NLD; ++i) {
+        for (int i = 0; i < NH; ++i) {
             const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
-            if (o < bytes)
-                *reinterpret_cast<uint4 *>(reg + dst + o) =
-                    *reinterpret_cast<const uint4 *>(src + a16 + o);
+            rh[i] = o < bh ? *reinterpret_cast<const uint4 *>(ph + o) : make_uint4(0, 0, 0, 0);
         }
-        return shift;
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+            const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
+            rz[i] = o < bz ? *reinterpret_cast<const uint4 *>(pz + o) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto commit = [&](int b) {  // registers -> LDS buffer b
+        uint8_t *dst = reg + b * BUF;
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
+            if (o < HB) *reinterpret_cast<uint4 *>(dst + o) = rh[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NZ; ++i) {
+            const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
+            if (HB + o < BUF) *reinterpret_cast<uint4 *>(dst + HB + o) = rz[i];
+        }
     };
     const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
                                    (kPhasePrimal << 30) | (uint32_t)c, t, g.rk);
-    const uint32_t Wn[4] = {wq.w0, wq.w1, wq.w2, wq.w3};
-    const uint32_t *zero = reinterpret_cast<const uint32_t *>(reg + SB - ZB);
-    const uint32_t rot = (uint32_t)(c + 2) & 31u;
-    int newx[4], qnv[4];
+    uint32_t drawn = 0;  // byte j: 1 + the new state of node j (0: not drawn)
+    // nodes without records are drawn from their base alone
+    double L[QM];
+    int j = 0;
+    uint32_t first = 0;
+    skip_empty(j, first);
+    int jn = j;
+    uint32_t fn = first;
+    if (jn < 4) issue(jn, fn);
+    int b = 0;
+    int jdone = 0;  // nodes [0, jdone) are drawn
+    auto draw_upto = [&](int jend) {  // draw record-less nodes below jend, in order
+        for (; jdone < jend; ++jdone) {
+            const int64_t node = quad * 4 + jdone;
+            if (node >= g.n) continue;
+            const int qn = UQ ? QM : (int)g.q[node];
+            double Lb[QM];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t node = quad * 4 + j;
-        newx[j] = -1;
-        qnv[j] = 0;
-        if (node >= g.n) continue;
+            for (int a = 0; a < QM; ++a) Lb[a] = (UQ || a < qn) ? g.base[node * QM + a] : 0.0;
+            const uint32_t U = (jdone == 0 ? wq.w0 : jdone == 1 ? wq.w1 : jdone == 2 ? wq.w2 : wq.w3) >> 8;
+            drawn |= (uint32_t)(draw_node<QM, UQ, EXP64>(Lb, qn, U) + 1) << (8 * jdone);
+        }
+    };
+    while (jn < 4) {
+        const uint32_t shh = sh_h, shz = sh_z;
+        commit(b);
+        const int jc = jn;
+        const uint32_t fc = fn;
+        const uint32_t nrec = min(sel(cnt, jc) - fc, (uint32_t)K);
+        // next chunk in flight while this one is read
+        fn = fc + nrec;
+        skip_empty(jn, fn);
+        if (jn < 4) issue(jn, fn);
+        const int64_t node = quad * 4 + jc;
         const int qn = UQ ? QM : (int)g.q[node];
-        qnv[j] = qn;
-        // half 0 starts from the node's base (lam and every c0), half 1 from 0
-        double L[QM];
+        if (fc == 0) {
+            draw_upto(jc);  // record-less nodes before this one
+            // half 0 starts from the node's base (lam and every c0), half 1 from 0
 #pragma unroll
-        for (int a = 0; a < QM; ++a)
-            L[a] = (p == 0 && (UQ || a < qn)) ? g.base[node * QM + a] : 0.0;
-        for (uint32_t first = 0; first < cnt[j]; first += K) {
-            const uint32_t nrec = (cnt[j] - first) < (uint32_t)K ? cnt[j] - first : (uint32_t)K;
-            const uint64_t r0 = (uint64_t)off[j] + first;
-            const uint32_t sh = copy16(reinterpret_cast<const uint8_t *>(g.rec_p), r0 * (RP * 8),
-                                       nrec * (RP * 8), 0);
-            const uint32_t sz = copy16(reinterpret_cast<const uint8_t *>(g.rec_z), r0 * (D * 4),
-                                       nrec * (D * 4), HB);
-            const double *hs = reinterpret_cast<const double *>(reg + sh);
-            const uint32_t *zs = reinterpret_cast<const uint32_t *>(reg + HB + sz);
-            for (uint32_t k = 0; k < nrec; k += 2) {
-                // half p takes record k + p; past the end it reads record k's h
-                // with an all-zero mask, which adds nothing
-                const bool has = k + p < nrec;
-                const double *h = hs + (has ? k + p : k) * RP;
-                const uint32_t *z = has ? zs + (k + p) * D : zero;
+            for (int a = 0; a < QM; ++a)
+                L[a] = (p == 0 && (UQ || a < qn)) ? g.base[node * QM + a] : 0.0;
+        }
+        const double *hs = reinterpret_cast<const double *>(reg + b * BUF + shh);
+        const uint32_t *zs = reinterpret_cast<const uint32_t *>(reg + b * BUF + HB + shz);
+        for (uint32_t k = 0; k < nrec; k += 2) {
+            // half p takes record k + p; past the end it reads record k's h
+            // with an all-zero mask, which adds nothing
+            const bool has = k + p < nrec;
+            const double *h = hs + (has ? k + p : k) * RP;
+            const uint32_t *z = has ? zs + (k + p) * D : zero;
 #pragma unroll
-                for (int s = 1; s < QM; ++s) {
-                    if (!UQ && s >= qn) break;
-                    double acc = L[s];
+            for (int s = 1; s < QM; ++s) {
+                if (!UQ && s >= qn) break;
+                double acc = L[s];
 #pragma unroll
-                    for (int o = 1; o < QM; ++o) {
-                        const int dp = (s - 1) * (QM - 1) + (o - 1);
-                        // rotating the word right by c + 2 puts chain c's bit at bit 30,
-                        // the one set bit of 2.0's high word
-                        const uint32_t hi = __builtin_amdgcn_alignbit(z[dp], z[dp], rot) & 0x40000000u;
-                        const double zf = __hiloint2double((int)hi, 0);
-                        acc = __builtin_fma(zf, h[dp], acc);
-                    }
-                    L[s] = acc;
+                for (int o = 1; o < QM; ++o) {
+                    const int dp = (s - 1) * (QM - 1) + (o - 1);
+                    // rotating the word right by c + 2 puts chain c's bit at
+                    // bit 30, the one set bit of 2.0's high word
+                    const uint32_t hi = __builtin_amdgcn_alignbit(z[dp], z[dp], rot) & 0x40000000u;
+                    acc = __builtin_fma(__hiloint2double((int)hi, 0), h[dp], acc);
                 }
+                L[s] = acc;
             }
         }
-        // both halves end with the same sum (IEEE addition is commutative)
+        if (fc + nrec >= sel(cnt, jc)) {
+            // both halves end with the same sum (IEEE addition is commutative)
 #pragma unroll
-        for (int s = 1; s < QM; ++s) L[s] += __shfl_xor(L[s], 32);
-        newx[j] = draw_node<QM, UQ, EXP64>(L, qn, Wn[j] >> 8);
+            for (int s = 1; s < QM; ++s) L[s] += __shfl_xor(L[s], 32);
+            const uint32_t U = (jc == 0 ? wq.w0 : jc == 1 ? wq.w1 : jc == 2 ? wq.w2 : wq.w3) >> 8;
+            drawn |= (uint32_t)(draw_node<QM, UQ, EXP64>(L, qn, U) + 1) << (8 * jc);
+            jdone = jc + 1;
+        }
+        b ^= 1;
     }
-    asm volatile("" ::"v"(sink));
+    draw_upto(4);
+    int newx[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) newx[jj] = (int)((drawn >> (8 * jj)) & 255u) - 1;
+    int qnv[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+        qnv[jj] = quad * 4 + jj < g.n ? (UQ ? QM : (int)g.q[quad * 4 + jj]) : 0;
     const bool writer = p == 0 && cvalid;
     if (count) {
         // the wave owns the quad's counters (one chain block; padded to whole quads)
         uint32_t row[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool nvalid = quad * 4 + j < g.n;
-            row[j] = 0u;
+        for (int jj = 0; jj < 4; ++jj) {
+            const bool nvalid = quad * 4 + jj < g.n;
+            row[jj] = 0u;
 #pragma unroll
             for (int a = 0; a < QM; ++a) {
-                const uint32_t v = g.counts[(quad * 4 + j) * QM + a] +
-                                   (uint32_t)__popcll(__ballot(nvalid && writer && newx[j] == a));
-                if (lane == a) row[j] = v;
+                const uint32_t v = g.counts[(quad * 4 + jj) * QM + a] +
+                                   (uint32_t)__popcll(__ballot(nvalid && writer && newx[jj] == a));
+                if (lane == a) row[jj] = v;
             }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t node = quad * 4 + j;
-            if (node < g.n && writer) g.x[node * g.C + c] = (uint8_t)newx[j];
+        for (int jj = 0; jj < 4; ++jj) {
+            const int64_t node = quad * 4 + jj;
+            if (node < g.n && writer) g.x[node * g.C + c] = (uint8_t)newx[jj];
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t node = quad * 4 + j;
-            if (node < g.n && lane < qnv[j]) g.counts[node * QM + lane] = row[j];
+        for (int jj = 0; jj < 4; ++jj) {
+            const int64_t node = quad * 4 + jj;
+            if (node < g.n && lane < qnv[jj]) g.counts[node * QM + lane] = row[jj];
         }
         return;
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t node = quad * 4 + j;
-        if (node < g.n && writer) g.x[node * g.C + c] = (uint8_t)newx[j];
+    for (int jj = 0; jj < 4; ++jj) {
+        const int64_t node = quad * 4 + jj;
+        if (node < g.n && writer) g.x[node * g.C + c] = (uint8_t)newx[jj];
     }
 }
 
