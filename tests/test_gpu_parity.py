@@ -365,3 +365,76 @@ def test_full_size_plain_grid_sampled():
     _say(f"  sampled draws {n_draw}, flagged {n_flag}")
     assert n_flag <= max(FLAG_BUDGET * n_draw, 3)
     s.close()
+
+
+def test_full_size_dynamic_sparse_sampled():
+    """Dynamic sparse workload at full size (Chung-Lu, 2^22 nodes, q=8, FP32
+    tables, 32 chains) in the launch configuration the benchmark times: sweeps
+    from init, one 1 % churn batch, a sweep on the edited graph, then one sweep
+    whose sampled edges and nodes -- the three largest hubs among them -- are
+    checked one by one by the oracle."""
+    import torch
+    n, q, C, seed = 1 << 22, 8, 32, 0
+    _say("[dynamic full-size] building the graph")
+    model = W.chung_lu(n, q, seed=0)
+    _say(f"[dynamic full-size] n={model.n} m={model.m}; uploading")
+    s = _sampler(model, C, seed, edge_capacity=model.m)
+    s.init()
+    s.sweep(2)
+    live_uid = _u64(s.uids).copy()
+    live_src, live_dst = model.src.copy(), model.dst.copy()
+    live_tab = np.arange(model.m)               # row of Lam for each live edge
+    churn = W.Churn(n, q, model.meta["weights"], seed=1)
+    rem, ns, nd, nL = churn.next_batch(live_uid)
+    _say(f"[dynamic full-size] churn: {len(rem)} removals and insertions")
+    s.remove_edges(torch.as_tensor(rem.view(np.int64), device=s.dev))
+    new_uid = _u64(s.insert_edges(ns, nd, nL))
+    keep = ~np.isin(live_uid, rem)
+    live_uid = np.concatenate([live_uid[keep], new_uid])
+    live_src = np.concatenate([live_src[keep], ns])
+    live_dst = np.concatenate([live_dst[keep], nd])
+    live_tab = np.concatenate([live_tab[keep], model.m + np.arange(len(ns))])
+    Lam_all = np.concatenate([model.Lam, nL])
+    s.sweep(1)
+    x_prev = s.state().cpu().numpy()
+    s.dual_phase()
+    deg = np.bincount(np.concatenate([live_src, live_dst]), minlength=n)
+    hubs = np.argsort(deg)[-3:]
+    rng = np.random.default_rng(0)
+    nodes = np.unique(np.concatenate([rng.choice(n, size=150, replace=False), hubs]))
+    ends = np.concatenate([live_src, live_dst])
+    order = np.argsort(ends, kind="stable")
+    se = ends[order]
+    lo, hi = np.searchsorted(se, nodes), np.searchsorted(se, nodes, side="right")
+    m_live = len(live_uid)
+    inc = {int(i): order[a:b] for i, a, b in zip(nodes, lo, hi)}
+    edges = np.unique(np.concatenate([v % m_live for v in inc.values()]))
+    _say(f"[dynamic full-size] {len(nodes)} nodes (max degree {deg.max()}), {len(edges)} edges")
+    th_g = _u64(s.duals(torch.as_tensor(live_uid[edges].view(np.int64), device=s.dev)))
+    s.primal_phase()
+    x_new = s.state().cpu().numpy()
+    t = s.t
+    subm = W.Model(model.q, model.lam, live_src[edges], live_dst[edges], Lam_all[live_tab[edges]])
+    dec = oracle.decompose(subm)
+    sub = {int(e): k for k, e in enumerate(edges)}
+    n_draw = n_flag = 0
+    for k, e in enumerate(edges):
+        for c in range(C):
+            th, fl = oracle.dual_edge(subm, dec, k, x_prev[live_src[e], c], x_prev[live_dst[e], c],
+                                      live_uid[e], c, t, seed)
+            assert ((int(th_g[k, c]) ^ th) & ~fl) == 0, (e, c)
+            n_draw += 49
+            n_flag += bin(fl).count("1")
+    for i in nodes:
+        es = inc[int(i)]
+        sides = (es >= m_live).astype(np.int32)
+        rows = np.array([sub[int(e % m_live)] for e in es], dtype=np.int64)
+        for c in range(C):
+            xo, fo = oracle.primal_node(subm, dec, int(i), rows, sides,
+                                        [th_g[r, c] for r in rows], c, t, seed)
+            assert fo or xo == x_new[i, c], (i, c)
+            n_draw += 1
+            n_flag += fo
+    _say(f"  sampled draws {n_draw}, flagged {n_flag}")
+    assert n_flag <= max(FLAG_BUDGET * n_draw, 3)
+    s.close()
