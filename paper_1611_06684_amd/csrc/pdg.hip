@@ -73,6 +73,14 @@ struct pdg_ctx {
     uint32_t *d_flag = nullptr;
     void *d_scratch = nullptr;
     int64_t scratch_bytes = 0;
+    // hubs (nodes with more than kHubThreshold incidence entries): their list,
+    // piece table and partial fields
+    uint32_t hub_thr = 0;        // threshold in force (0: hubs are not split)
+    int64_t nh = 0, np = 0;      // hubs, pieces
+    uint32_t *d_hub = nullptr;   // hnode[nh] | hpfirst[nh + 1] | pnode[np] | pfirst[np] | pn[np]
+    int64_t hub_cap = 0;         // u32 capacity of d_hub
+    double *d_part = nullptr;    // [np][CB][QM - 1][64]
+    int64_t part_cap = 0;        // doubles
     pdg::Store st;
     std::string err;
 };
@@ -186,6 +194,7 @@ static Graph make_graph(pdg_ctx *ctx)
     g.hwm = ctx->st.hwm;
     g.C = ctx->C;
     g.CB = (int32_t)cdiv(ctx->C, 64);
+    g.heavy = ctx->hub_thr;
     g.k0 = (uint32_t)ctx->cfg.seed;
     g.k1 = (uint32_t)(ctx->cfg.seed >> 32);
     g.rk = make_round_keys(ctx->cfg.seed);
@@ -270,6 +279,25 @@ static void launch_dual(pdg_ctx *ctx, uint32_t t)
         launch_dual_u<false>(ctx, t);
 }
 
+template <int QM, bool UQ, bool E64>
+static void launch_hubs_q(pdg_ctx *ctx, const Graph &g, uint32_t t, int count)
+{
+    const uint32_t *hn = ctx->d_hub, *hp = hn + ctx->nh, *pnode = hp + ctx->nh + 1;
+    const uint32_t *pf = pnode + ctx->np, *pn = pf + ctx->np;
+    const int64_t wp = ctx->np * ctx->CB, wf = ctx->nh * ctx->CB;
+    if (ctx->LPI == 64) {
+        k_hub_pieces<QM, 64><<<grid_for(wp * 64), 256, 0, ctx->stream>>>(g, ctx->np, pnode, pf, pn,
+                                                                         ctx->d_part);
+        k_hub_finish<QM, UQ, E64, 64><<<grid_for(wf * 64), 256, 0, ctx->stream>>>(
+            g, ctx->nh, hn, hp, ctx->d_part, t, count);
+    } else {
+        k_hub_pieces<QM, 32><<<grid_for(wp * 64), 256, 0, ctx->stream>>>(g, ctx->np, pnode, pf, pn,
+                                                                         ctx->d_part);
+        k_hub_finish<QM, UQ, E64, 32><<<grid_for(wf * 64), 256, 0, ctx->stream>>>(
+            g, ctx->nh, hn, hp, ctx->d_part, t, count);
+    }
+}
+
 template <bool UQ, bool E64>
 static void launch_primal_e(pdg_ctx *ctx, uint32_t t, int count)
 {
@@ -282,6 +310,17 @@ static void launch_primal_e(pdg_ctx *ctx, uint32_t t, int count)
     case 6: primal_q<6, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
     case 7: primal_q<7, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
     default: primal_q<8, UQ, E64>(ctx->LPI, g, t, count, ctx->CB, ctx->stream); break;
+    }
+    if (g.heavy && ctx->nh) {
+        switch (ctx->QM) {
+        case 2: launch_hubs_q<2, UQ, E64>(ctx, g, t, count); break;
+        case 3: launch_hubs_q<3, UQ, E64>(ctx, g, t, count); break;
+        case 4: launch_hubs_q<4, UQ, E64>(ctx, g, t, count); break;
+        case 5: launch_hubs_q<5, UQ, E64>(ctx, g, t, count); break;
+        case 6: launch_hubs_q<6, UQ, E64>(ctx, g, t, count); break;
+        case 7: launch_hubs_q<7, UQ, E64>(ctx, g, t, count); break;
+        default: launch_hubs_q<8, UQ, E64>(ctx, g, t, count); break;
+        }
     }
 }
 
@@ -582,12 +621,72 @@ static void launch_node_base(pdg_ctx *ctx, int64_t nn, const uint32_t *dnodes)
     }
 }
 
+// Hub list and piece table from the host's segment counts (the device holds
+// the same counts).  Hubs are split only with 32 or more chains and while a
+// hub piece kernel's LDS chunk holds at least the records of one step.
+static pdg_status rebuild_hubs(pdg_ctx *ctx)
+{
+    Store &st = ctx->st;
+    ctx->hub_thr = 0;
+    ctx->nh = ctx->np = 0;
+    if (ctx->LPI < 32) return PDG_OK;
+    const int64_t D = ctx->D, RP = ctx->RP;
+    const int64_t zr = ctx->LPI == 64 ? 2 * D * ctx->CB : D;
+    const int64_t zb = (8 * D + 15) / 16 * 16;
+    const int64_t K = (4096 - zb - 48) / (RP * 8 + 4 * zr);
+    if (K < (ctx->LPI == 32 ? 2 : 1)) return PDG_OK;
+    std::vector<uint32_t> hn, hp{0}, pn_node, pf, pn;
+    for (int64_t i = 0; i < ctx->n; ++i) {
+        const uint32_t c = st.cnt[i];
+        if (c <= kHubThreshold) continue;
+        hn.push_back((uint32_t)i);
+        for (uint32_t f = 0; f < c; f += kHubPiece) {
+            pn_node.push_back((uint32_t)i);
+            pf.push_back(f);
+            pn.push_back(std::min(kHubPiece, c - f));
+        }
+        hp.push_back((uint32_t)pf.size());
+    }
+    const int64_t nh = (int64_t)hn.size(), np = (int64_t)pf.size();
+    if (nh == 0) return PDG_OK;
+    const int64_t words = nh + (nh + 1) + 3 * np;
+    if (words > ctx->hub_cap) {
+        if (ctx->d_hub) PDG_HIP(ctx, hipFree(ctx->d_hub));
+        ctx->d_hub = nullptr;
+        ctx->hub_cap = 0;
+        PDG_TRY(dalloc(ctx, (void **)&ctx->d_hub, words * 4));
+        ctx->hub_cap = words;
+    }
+    const int64_t pd = np * ctx->CB * (ctx->QM - 1) * 64;
+    if (pd > ctx->part_cap) {
+        if (ctx->d_part) PDG_HIP(ctx, hipFree(ctx->d_part));
+        ctx->d_part = nullptr;
+        ctx->part_cap = 0;
+        PDG_TRY(dalloc(ctx, (void **)&ctx->d_part, pd * 8));
+        ctx->part_cap = pd;
+    }
+    std::vector<uint32_t> all;
+    all.reserve(words);
+    all.insert(all.end(), hn.begin(), hn.end());
+    all.insert(all.end(), hp.begin(), hp.end());
+    all.insert(all.end(), pn_node.begin(), pn_node.end());
+    all.insert(all.end(), pf.begin(), pf.end());
+    all.insert(all.end(), pn.begin(), pn.end());
+    PDG_HIP(ctx, hipMemcpyAsync(ctx->d_hub, all.data(), words * 4, hipMemcpyHostToDevice,
+                                ctx->stream));
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->nh = nh;
+    ctx->np = np;
+    ctx->hub_thr = kHubThreshold;
+    return PDG_OK;
+}
+
 static void free_all(pdg_ctx *ctx)
 {
     void *ps[] = {ctx->d_q,     ctx->d_lam,   ctx->d_x,     ctx->d_counts, ctx->d_src,
                   ctx->d_dst,   ctx->d_uid,   ctx->d_sq,    ctx->d_params, ctx->d_ipos,
                   ctx->d_off,   ctx->d_cnt,   ctx->d_pool,  ctx->d_rec_p,  ctx->d_rec_z,
-                  ctx->d_flag,  ctx->d_scratch, ctx->d_base};
+                  ctx->d_flag,  ctx->d_scratch, ctx->d_base, ctx->d_hub, ctx->d_part};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -833,6 +932,7 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     // device: incidence structure and records (moves, ipos), then slot
     // arrays, decomposition of the new tables, and their records
     PDG_TRY(upload(ctx, P, touched));
+    PDG_TRY(rebuild_hubs(ctx));
     const int64_t nn = (int64_t)touched.size();
     std::vector<uint32_t> hnodes(touched.begin(), touched.end());
     void *s;

@@ -79,6 +79,8 @@ struct Graph {
     int64_t hwm;                          // slots [0, hwm) may be live
     int32_t C;
     int32_t CB;                           // blocks of 64 chains (1 when C <= 64)
+    uint32_t heavy;                       // a node with more incidence entries is a hub,
+                                          // drawn by the hub kernels (0: none)
     uint32_t k0, k1;                      // generator key
     RoundKeys rk;                         // its ten round keys
 };
@@ -620,11 +622,16 @@ __global__ __launch_bounds__(256) void k_primal64(Graph g, uint32_t t, int count
     const int64_t quad = lm.item;
     const bool cvalid = lm.c < g.C;
     uint32_t off[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+    uint32_t hub = 0;  // bit j: node j is a hub (drawn by the hub kernels)
     if (quad * 4 < g.n) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             off[j] = g.inc_off[quad * 4 + j];
             cnt[j] = g.inc_cnt[quad * 4 + j];
+            if (g.heavy && cnt[j] > g.heavy) {
+                hub |= 1u << j;
+                cnt[j] = 0;
+            }
         }
     }
     // records [first, first + nrec) of node j into its LDS region; returns the
@@ -680,7 +687,7 @@ __global__ __launch_bounds__(256) void k_primal64(Graph g, uint32_t t, int count
         const int64_t node = quad * 4 + j;
         newx[j] = -1;
         qnv[j] = 0;
-        if (node >= g.n) continue;
+        if (node >= g.n || ((hub >> j) & 1u)) continue;
         const int qn = UQ ? QM : (int)g.q[node];
         qnv[j] = qn;
         // the theta-free part (lam and every c0) is the node's base
@@ -740,7 +747,7 @@ __global__ __launch_bounds__(256) void k_primal64(Graph g, uint32_t t, int count
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t node = quad * 4 + j;
-            if (node < g.n && cvalid) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
+            if (newx[j] >= 0 && cvalid) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -752,7 +759,7 @@ __global__ __launch_bounds__(256) void k_primal64(Graph g, uint32_t t, int count
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t node = quad * 4 + j;
-        const bool nvalid = node < g.n;
+        const bool nvalid = node < g.n && newx[j] >= 0;
         if (nvalid && cvalid) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
         if (count) {
 #pragma unroll
@@ -796,10 +803,15 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
     const bool cvalid = c < g.C;
     if (quad * 4 >= g.n) return;
     uint32_t off[4], cnt[4];
+    uint32_t hub = 0;  // bit j: node j is a hub (drawn by the hub kernels)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         off[j] = g.inc_off[quad * 4 + j];
         cnt[j] = quad * 4 + j < g.n ? g.inc_cnt[quad * 4 + j] : 0u;
+        if (g.heavy && cnt[j] > g.heavy) {
+            hub |= 1u << j;
+            cnt[j] = 0;
+        }
     }
     uint8_t *reg = lds[wib];
     if (lane < ZB / 16)
@@ -868,7 +880,7 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
     auto draw_upto = [&](int jend) {  // draw record-less nodes below jend, in order
         for (; jdone < jend; ++jdone) {
             const int64_t node = quad * 4 + jdone;
-            if (node >= g.n) continue;
+            if (node >= g.n || ((hub >> jdone) & 1u)) continue;
             const int qn = UQ ? QM : (int)g.q[node];
             double Lb[QM];
 #pragma unroll
@@ -933,10 +945,10 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
     int newx[4];
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) newx[jj] = (int)((drawn >> (8 * jj)) & 255u) - 1;
-    int qnv[4];
+    int qnv[4];  // 0 for nodes this wave does not draw
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
-        qnv[jj] = quad * 4 + jj < g.n ? (UQ ? QM : (int)g.q[quad * 4 + jj]) : 0;
+        qnv[jj] = newx[jj] >= 0 ? (UQ ? QM : (int)g.q[quad * 4 + jj]) : 0;
     const bool writer = p == 0 && cvalid;
     if (count) {
         // the wave owns the quad's counters (one chain block; padded to whole quads)
@@ -955,19 +967,169 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const int64_t node = quad * 4 + jj;
-            if (node < g.n && writer) g.x[node * g.C + c] = (uint8_t)newx[jj];
+            if (newx[jj] >= 0 && writer) g.x[node * g.C + c] = (uint8_t)newx[jj];
         }
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const int64_t node = quad * 4 + jj;
-            if (node < g.n && lane < qnv[jj]) g.counts[node * QM + lane] = row[jj];
+            if (lane < qnv[jj]) g.counts[node * QM + lane] = row[jj];
         }
         return;
     }
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
         const int64_t node = quad * 4 + jj;
-        if (node < g.n && writer) g.x[node * g.C + c] = (uint8_t)newx[jj];
+        if (newx[jj] >= 0 && writer) g.x[node * g.C + c] = (uint8_t)newx[jj];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a4 for hubs.  A node with more than kHubThreshold incidence entries is a
+// hub: the quad kernels skip it, and its records are split into pieces of at
+// most kHubPiece so that one hub's work spreads over many waves.
+// k_hub_pieces: one wave per (piece, chain block) sums sum_records sum_o
+// 2 theta h over the piece (records staged in the wave's LDS region, the
+// chain's mask bit tested as in k_primal32); with LPI = 32 the halves take
+// alternate records and are added at the end.  The partial field goes to
+// part[((piece * CB + cb) * (QM - 1) + s - 1) * 64 + lane].
+// k_hub_finish: one wave per (hub, chain block) adds the node's base and its
+// pieces' partial fields in piece order, then draws, stores x and counts.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kHubThreshold = 256;
+constexpr uint32_t kHubPiece = 128;
+
+template <int QM, int LPI>
+__global__ __launch_bounds__(256) void k_hub_pieces(Graph g, int64_t np,
+                                                    const uint32_t *__restrict__ pnode,
+                                                    const uint32_t *__restrict__ pfirst,
+                                                    const uint32_t *__restrict__ pn,
+                                                    double *__restrict__ part)
+{
+    constexpr int D = dim_d(QM);
+    constexpr int RP = rec_len(QM);
+    constexpr int BUF = 4096;                   // LDS bytes per wave
+    constexpr int ZB = (8 * D + 15) / 16 * 16;  // zero mask block
+    constexpr int NLD = BUF / 1024;
+    __shared__ __align__(16) uint8_t lds[4][BUF];
+    const int lane = threadIdx.x & 63;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    const int CB = g.CB;
+    const int64_t piece = w / CB;
+    const int cb = (int)(w - piece * CB);
+    if (piece >= np) return;
+    const uint32_t node = pnode[piece];
+    const uint64_t r0 = (uint64_t)g.inc_off[node] + pfirst[piece];
+    const uint32_t n = pn[piece];
+    const int p = LPI == 32 ? lane >> 5 : 0;
+    constexpr uint32_t PR = LPI == 32 ? 2u : 1u;                    // records per step
+    const uint32_t zr = LPI == 64 ? 2u * D * (uint32_t)CB : (uint32_t)D;  // u32 words per record
+    const uint32_t zsel = LPI == 64 ? (uint32_t)(cb * 2 * D + (lane >> 5)) : 0u;
+    constexpr uint32_t ZSTEP = LPI == 64 ? 2u : 1u;
+    const uint32_t rot = (uint32_t)((lane & 31) + 2) & 31u;
+    const uint32_t K = (uint32_t)(BUF - ZB - 48) / (uint32_t)(RP * 8 + 4 * zr);
+    const uint32_t HB = (16 + K * (RP * 8) + 15) & ~15u;
+    uint8_t *reg = lds[wib];
+    if (lane < ZB / 16)
+        *reinterpret_cast<uint4 *>(reg + BUF - ZB + 16 * lane) = make_uint4(0, 0, 0, 0);
+    const uint32_t *zero = reinterpret_cast<const uint32_t *>(reg + BUF - ZB);
+    auto copy16 = [&](const uint8_t *src, uint64_t a, uint32_t nb, uint32_t dst) -> uint32_t {
+        const uint64_t a16 = a & ~(uint64_t)15;
+        const uint32_t shift = (uint32_t)(a - a16);
+        const uint32_t bytes = shift + nb;
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
+            if (o < bytes)
+                *reinterpret_cast<uint4 *>(reg + dst + o) =
+                    *reinterpret_cast<const uint4 *>(src + a16 + o);
+        }
+        return shift;
+    };
+    double L[QM];
+#pragma unroll
+    for (int a = 0; a < QM; ++a) L[a] = 0.0;
+    for (uint32_t first = 0; first < n; first += K) {
+        const uint32_t nrec = min(n - first, K);
+        const uint32_t sh = copy16(reinterpret_cast<const uint8_t *>(g.rec_p),
+                                   (r0 + first) * (RP * 8), nrec * (RP * 8), 0);
+        const uint32_t sz = copy16(reinterpret_cast<const uint8_t *>(g.rec_z),
+                                   (r0 + first) * zr * 4, nrec * zr * 4, HB);
+        const double *hs = reinterpret_cast<const double *>(reg + sh);
+        const uint32_t *zs = reinterpret_cast<const uint32_t *>(reg + HB + sz);
+        for (uint32_t k = 0; k < nrec; k += PR) {
+            // with LPI = 32 half p takes record k + p; past the end it reads
+            // record k's h with an all-zero mask, which adds nothing
+            const bool has = k + p < nrec;
+            const double *h = hs + (has ? k + p : k) * RP;
+            const uint32_t *z = has ? zs + (k + p) * zr + zsel : zero;
+#pragma unroll
+            for (int s = 1; s < QM; ++s) {
+                double acc = L[s];
+#pragma unroll
+                for (int o = 1; o < QM; ++o) {
+                    const int dp = (s - 1) * (QM - 1) + (o - 1);
+                    const uint32_t wz = z[dp * ZSTEP];
+                    const uint32_t hi = __builtin_amdgcn_alignbit(wz, wz, rot) & 0x40000000u;
+                    acc = __builtin_fma(__hiloint2double((int)hi, 0), h[dp], acc);
+                }
+                L[s] = acc;
+            }
+        }
+    }
+    if (LPI == 32) {
+#pragma unroll
+        for (int s = 1; s < QM; ++s) L[s] += __shfl_xor(L[s], 32);
+    }
+#pragma unroll
+    for (int s = 1; s < QM; ++s)
+        part[((piece * CB + cb) * (QM - 1) + (s - 1)) * 64 + lane] = L[s];
+}
+
+template <int QM, bool UQ, bool EXP64, int LPI>
+__global__ __launch_bounds__(256) void k_hub_finish(Graph g, int64_t nh,
+                                                    const uint32_t *__restrict__ hnode,
+                                                    const uint32_t *__restrict__ hpfirst,
+                                                    const double *__restrict__ part, uint32_t t,
+                                                    int count)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int CB = g.CB;
+    const int64_t k = w / CB;
+    const int cb = (int)(w - k * CB);
+    if (k >= nh) return;
+    const uint64_t node = hnode[k];
+    const int c = LPI == 64 ? cb * 64 + lane : (lane & 31);
+    const bool cvalid = c < g.C && (LPI == 64 || lane < 32);
+    const int qn = UQ ? QM : (int)g.q[node];
+    double L[QM];
+#pragma unroll
+    for (int a = 0; a < QM; ++a) L[a] = (UQ || a < qn) ? g.base[node * QM + a] : 0.0;
+    for (uint32_t pc = hpfirst[k]; pc < hpfirst[k + 1]; ++pc) {
+#pragma unroll
+        for (int s = 1; s < QM; ++s)
+            if (UQ || s < qn) L[s] += part[(((int64_t)pc * CB + cb) * (QM - 1) + (s - 1)) * 64 + lane];
+    }
+    // the node's word of its quad's call, as the quad kernels draw it
+    const uint64_t quad = node >> 2;
+    const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                   (kPhasePrimal << 30) | (uint32_t)c, t, g.rk);
+    const uint32_t U = word_at(wq, (int)(node & 3)) >> 8;
+    const int xn = draw_node<QM, UQ, EXP64>(L, qn, U);
+    if (cvalid) g.x[node * g.C + c] = (uint8_t)xn;
+    if (count) {
+#pragma unroll
+        for (int a = 0; a < QM; ++a) {
+            const uint64_t bal = __ballot(cvalid && xn == a);
+            if (lane == 0 && a < qn && bal != 0) {
+                if (CB == 1)  // this wave owns the node's counters
+                    g.counts[node * QM + a] += (uint32_t)__popcll(bal);
+                else
+                    atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(bal));
+            }
+        }
     }
 }
 

@@ -77,6 +77,36 @@ def _models():
     yield "grid_16x16_q2_f32_C100", W.table_grid(16, 16, 2, seed=5, pair_std=1.0), 100
     yield "ising_10x10_f64_C13", W.ising_grid(10, 10, seed=6, J_half_range=0.8), 13
     yield "chung_lu_4096_q8_f32_C32", W.chung_lu(4096, 8, seed=7), 32
+    # hubs: nodes with more incidences than a quad kernel takes (split into pieces)
+    yield "hubs_q4_f32_C64", _hub_graph(900, [4], 3, 8), 64
+    yield "hubs_mixed_q235_f32_C32", _hub_graph(700, [2, 3, 5], 4, 9), 32
+    yield "hubs_q2_f32_C100", _hub_graph(600, [2], 2, 10), 100
+
+
+def _hub_graph(n, qs, n_hubs, seed):
+    """n nodes with q uniform from qs; hub h (h < n_hubs) is joined to 300 + 130 h
+    other nodes (as src or dst alternately), plus 2 n random edges; tables
+    N(0, 0.5), entries beyond a node's q zero, unaries N(0, 1), FP32."""
+    rng = np.random.default_rng(seed)
+    q = rng.choice(np.asarray(qs), size=n).astype(np.int32)
+    src, dst = [], []
+    for h in range(n_hubs):
+        others = rng.choice(np.setdiff1d(np.arange(n), [h]), size=300 + 130 * h, replace=False)
+        for k, o in enumerate(others):
+            src.append(h if k % 2 == 0 else o)
+            dst.append(o if k % 2 == 0 else h)
+    a = rng.integers(0, n, 2 * n)
+    b = (a + 1 + rng.integers(0, n - 1, 2 * n)) % n
+    src = np.concatenate([np.asarray(src), a]).astype(np.int32)
+    dst = np.concatenate([np.asarray(dst), b]).astype(np.int32)
+    qm = int(max(qs))
+    Lam = rng.normal(0.0, 0.5, size=(len(src), qm, qm))
+    lam = rng.normal(0.0, 1.0, size=(n, qm))
+    ar = np.arange(qm)
+    Lam[np.broadcast_to(ar[None, :, None] >= q[src][:, None, None], Lam.shape)] = 0.0
+    Lam[np.broadcast_to(ar[None, None, :] >= q[dst][:, None, None], Lam.shape)] = 0.0
+    lam[ar[None, :] >= q[:, None]] = 0.0
+    return W.Model(q, lam.astype(np.float32), src, dst, Lam.astype(np.float32), f"hubs_{n}")
 
 
 @pytest.mark.parametrize("name,model,C", list(_models()), ids=[m[0] for m in _models()])
