@@ -24,15 +24,24 @@ namespace pdg {
 
 static thread_local std::string g_global_err;
 
+// Host mirror of the edge store, laid out so that an edit touches one cache
+// line per slot and one per node.
+struct SlotRec {
+    uint64_t uid;        // 0 = free
+    int32_t src, dst;
+    uint32_t pos0, pos1; // position of the slot's entry in its src / dst segment
+    uint32_t gen;        // generation of the slot (high word of its uids)
+    uint32_t pad;
+};
+struct NodeRec {
+    uint32_t off, cnt, cap, nlive;  // segment [off, off + cnt) of cap entries, live ones
+};
 struct Store {
     int64_t S = 0;
-    std::vector<uint64_t> uid;     // [S], 0 = free
-    std::vector<uint32_t> gen;     // [S]
-    std::vector<int32_t> src, dst; // [S]
-    std::vector<uint32_t> pos0, pos1;
+    std::vector<SlotRec> slot;    // [S]
     std::vector<int32_t> free_stack;
     int64_t hwm = 0, live = 0;
-    std::vector<uint32_t> off, cnt, cap, nlive;  // per node
+    std::vector<NodeRec> node;    // [n]
     std::vector<uint32_t> mark;                  // per node, zero between calls (edit scratch)
     std::vector<uint32_t> pool;
     int64_t pool_top = 0;
@@ -407,6 +416,15 @@ static void launch_check(int qm, bool f64, int64_t m, const int32_t *s, const in
 // ---------------------------------------------------------------- edge store
 static uint32_t slack_for(uint32_t k) { return std::max<uint32_t>(2u, k / 4u); }
 
+// Edits touch the host mirror at random places; the loops below request the
+// lines of later iterations ahead of time (distance kAhead).
+constexpr int64_t kAhead = 16;
+template <typename T>
+static inline void prefetch_w(const T *p)
+{
+    __builtin_prefetch(p, 1, 0);
+}
+
 struct Patches {
     std::vector<uint32_t> idx, val;        // pool entries
     bool full = false;                     // whole pool and every header re-laid
@@ -418,9 +436,9 @@ static void note_entry(Store &st, uint32_t e, uint32_t w, uint32_t rec, Patches 
 {
     const uint32_t slot = e >> 1;
     if (e & 1u)
-        st.pos1[slot] = w;
+        st.slot[slot].pos1 = w;
     else
-        st.pos0[slot] = w;
+        st.slot[slot].pos0 = w;
     P.ip_key.push_back(2u * slot + (e & 1u));
     P.ip_val.push_back(rec);
 }
@@ -433,7 +451,7 @@ static pdg_status full_compact(pdg_ctx *ctx, const std::vector<uint32_t> &need, 
     std::vector<uint32_t> noff(n), ncap(n);
     uint64_t total = 0;
     for (int64_t i = 0; i < n; ++i) {
-        const uint32_t want = st.nlive[i] + need[i];
+        const uint32_t want = st.node[i].nlive + need[i];
         ncap[i] = want ? want + slack_for(want) : 0;
         noff[i] = (uint32_t)total;
         total += ncap[i];
@@ -448,18 +466,18 @@ static pdg_status full_compact(pdg_ctx *ctx, const std::vector<uint32_t> &need, 
     P.mv_to.clear();
     for (int64_t i = 0; i < n; ++i) {
         uint32_t w = 0;
-        for (uint32_t k = 0; k < st.cnt[i]; ++k) {
-            const uint32_t e = st.pool[st.off[i] + k];
+        for (uint32_t k = 0; k < st.node[i].cnt; ++k) {
+            const uint32_t e = st.pool[st.node[i].off + k];
             if (e == kTomb) continue;
             npool[noff[i] + w] = e;
-            P.mv_from.push_back(st.off[i] + k);
+            P.mv_from.push_back(st.node[i].off + k);
             P.mv_to.push_back(noff[i] + w);
             note_entry(st, e, w, noff[i] + w, P);
             ++w;
         }
-        st.off[i] = noff[i];
-        st.cnt[i] = w;
-        st.cap[i] = ncap[i];
+        st.node[i].off = noff[i];
+        st.node[i].cnt = w;
+        st.node[i].cap = ncap[i];
     }
     st.pool.swap(npool);
     st.pool_top = (int64_t)total;
@@ -469,38 +487,38 @@ static pdg_status full_compact(pdg_ctx *ctx, const std::vector<uint32_t> &need, 
 static void relocate(pdg_ctx *ctx, int64_t i, uint32_t need, Patches &P)
 {
     Store &st = ctx->st;
-    const uint32_t want = st.nlive[i] + need;
+    const uint32_t want = st.node[i].nlive + need;
     const uint32_t ncap = want + slack_for(want);
     const uint32_t noff = (uint32_t)st.pool_top;
     st.pool_top += ncap;
     uint32_t w = 0;
-    for (uint32_t k = 0; k < st.cnt[i]; ++k) {
-        const uint32_t e = st.pool[st.off[i] + k];
+    for (uint32_t k = 0; k < st.node[i].cnt; ++k) {
+        const uint32_t e = st.pool[st.node[i].off + k];
         if (e == kTomb) continue;
         st.pool[noff + w] = e;
         P.idx.push_back(noff + w);
         P.val.push_back(e);
-        P.mv_from.push_back(st.off[i] + k);
+        P.mv_from.push_back(st.node[i].off + k);
         P.mv_to.push_back(noff + w);
         note_entry(st, e, w, noff + w, P);
         ++w;
     }
-    st.off[i] = noff;
-    st.cnt[i] = w;
-    st.cap[i] = ncap;
+    st.node[i].off = noff;
+    st.node[i].cnt = w;
+    st.node[i].cap = ncap;
 }
 
 static void append(pdg_ctx *ctx, int64_t i, uint32_t e, Patches &P)
 {
     Store &st = ctx->st;
-    const uint32_t p = st.cnt[i]++;
-    st.pool[st.off[i] + p] = e;
+    const uint32_t p = st.node[i].cnt++;
+    st.pool[st.node[i].off + p] = e;
     if (!P.full) {
-        P.idx.push_back(st.off[i] + p);
+        P.idx.push_back(st.node[i].off + p);
         P.val.push_back(e);
     }
-    note_entry(st, e, p, st.off[i] + p, P);
-    st.nlive[i]++;
+    note_entry(st, e, p, st.node[i].off + p, P);
+    st.node[i].nlive++;
 }
 
 // Upload a host vector to a fresh region of the scratch buffer.
@@ -527,8 +545,8 @@ static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &t
     std::vector<uint32_t> hn(nn), ho(nn), hc(nn);
     for (int64_t k = 0; k < nn; ++k) {
         hn[k] = (uint32_t)touched[k];
-        ho[k] = st.off[touched[k]];
-        hc[k] = st.cnt[touched[k]];
+        ho[k] = st.node[touched[k]].off;
+        hc[k] = st.node[touched[k]].cnt;
     }
     void *s;
     PDG_TRY(scratch(ctx, 4 * (2 * nmv + 2 * np + 3 * nn + 2 * nip) + 8 * 256, &s));
@@ -564,9 +582,14 @@ static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &t
         }
         PDG_HIP(ctx, hipMemcpyAsync(npool, st.pool.data(), cap * 4, hipMemcpyHostToDevice,
                                     ctx->stream));
-        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_off, st.off.data(), (size_t)ctx->n * 4,
+        std::vector<uint32_t> all_off((size_t)ctx->n), all_cnt((size_t)ctx->n);
+        for (int64_t i = 0; i < ctx->n; ++i) {
+            all_off[i] = st.node[i].off;
+            all_cnt[i] = st.node[i].cnt;
+        }
+        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_off, all_off.data(), (size_t)ctx->n * 4,
                                     hipMemcpyHostToDevice, ctx->stream));
-        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_cnt, st.cnt.data(), (size_t)ctx->n * 4,
+        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_cnt, all_cnt.data(), (size_t)ctx->n * 4,
                                     hipMemcpyHostToDevice, ctx->stream));
         PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
         if (ctx->d_pool) PDG_HIP(ctx, hipFree(ctx->d_pool));
@@ -637,7 +660,7 @@ static pdg_status rebuild_hubs(pdg_ctx *ctx)
     if (K < (ctx->LPI == 32 ? 2 : 1)) return PDG_OK;
     std::vector<uint32_t> hn, hp{0}, pn_node, pf, pn;
     for (int64_t i = 0; i < ctx->n; ++i) {
-        const uint32_t c = st.cnt[i];
+        const uint32_t c = st.node[i].cnt;
         if (c <= kHubThreshold) continue;
         hn.push_back((uint32_t)i);
         for (uint32_t f = 0; f < c; f += kHubPiece) {
@@ -776,12 +799,7 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
     Store &st = ctx->st;
     try {
         st.S = S;
-        st.uid.assign(S, 0);
-        st.gen.assign(S, 0);
-        st.src.assign(S, 0);
-        st.dst.assign(S, 0);
-        st.pos0.assign(S, 0);
-        st.pos1.assign(S, 0);
+        st.slot.assign(S, SlotRec{0, 0, 0, 0, 0, 0, 0});
         st.free_stack.resize(S);
         for (int64_t j = 0; j < S; ++j) st.free_stack[j] = (int32_t)(S - 1 - j);
     } catch (...) {
@@ -829,10 +847,7 @@ pdg_status pdg_set_nodes(pdg_ctx *ctx, int64_t n, const int32_t *d_q, const void
         ctx->uq = std::all_of(hq.begin(), hq.end(), [&](int32_t v) { return v == ctx->QM; });
     }
     Store &st = ctx->st;
-    st.off.assign(n, 0);
-    st.cnt.assign(n, 0);
-    st.cap.assign(n, 0);
-    st.nlive.assign(n, 0);
+    st.node.assign(n, NodeRec{0, 0, 0, 0});
     st.mark.assign(n, 0);
     ctx->n = n;
     PDG_HIP(ctx, hipMemsetAsync(ctx->d_off, 0, n * 4, ctx->stream));
@@ -867,7 +882,7 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
         if (hs[k] == hd[k]) return fail(ctx, PDG_EINVAL, "self-loop is not a pairwise factor");
     }
     for (int64_t k = 0; k < m; ++k)
-        if (st.gen[st.free_stack[st.free_stack.size() - 1 - k]] == 0xFFFFFFFFu)
+        if (st.slot[st.free_stack[st.free_stack.size() - 1 - k]].gen == 0xFFFFFFFFu)
             return fail(ctx, PDG_ECAPACITY, "uid space of a slot exhausted");
     // tables must be finite before anything changes
     PDG_TRY(clear_flag(ctx));
@@ -881,16 +896,18 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     // slots and uids
     std::vector<int32_t> slots(m);
     std::vector<uint64_t> uids(m);
+    const int64_t fs0 = (int64_t)st.free_stack.size();
     for (int64_t k = 0; k < m; ++k) {
+        if (k + kAhead < m) prefetch_w(&st.slot[st.free_stack[fs0 - 1 - (k + kAhead)]]);
         const int32_t s = st.free_stack.back();
         st.free_stack.pop_back();
-        st.gen[s] += 1;
-        const uint64_t u = ((uint64_t)st.gen[s] << 32) | (uint32_t)s;
+        st.slot[s].gen += 1;
+        const uint64_t u = ((uint64_t)st.slot[s].gen << 32) | (uint32_t)s;
         slots[k] = s;
         uids[k] = u;
-        st.uid[s] = u;
-        st.src[s] = hs[k];
-        st.dst[s] = hd[k];
+        st.slot[s].uid = u;
+        st.slot[s].src = hs[k];
+        st.slot[s].dst = hd[k];
         st.hwm = std::max<int64_t>(st.hwm, (int64_t)s + 1);
     }
     st.live += m;
@@ -901,6 +918,10 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     try {
         touched.reserve(2 * m);
         for (int64_t k = 0; k < m; ++k) {
+            if (k + kAhead < m) {
+                prefetch_w(&need[hs[k + kAhead]]);
+                prefetch_w(&need[hd[k + kAhead]]);
+            }
             if (need[hs[k]]++ == 0) touched.push_back(hs[k]);
             if (need[hd[k]]++ == 0) touched.push_back(hd[k]);
         }
@@ -914,18 +935,34 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
         ~Reset() { for (int64_t i : idx) v[i] = 0; }
     } reset_need{need, touched};
     uint64_t room = 0;
-    for (int64_t i : touched)
-        if (st.cnt[i] + need[i] > st.cap[i]) {
-            const uint32_t want = st.nlive[i] + need[i];
+    for (size_t k = 0; k < touched.size(); ++k) {
+        if (k + kAhead < touched.size()) prefetch_w(&st.node[touched[k + kAhead]]);
+        const int64_t i = touched[k];
+        if (st.node[i].cnt + need[i] > st.node[i].cap) {
+            const uint32_t want = st.node[i].nlive + need[i];
             room += want + slack_for(want);
         }
+    }
     if ((uint64_t)st.pool_top + room > (uint64_t)st.pool.size()) {
         PDG_TRY(full_compact(ctx, need, P));
     } else {
         for (int64_t i : touched)
-            if (st.cnt[i] + need[i] > st.cap[i]) relocate(ctx, i, need[i], P);
+            if (st.node[i].cnt + need[i] > st.node[i].cap) relocate(ctx, i, need[i], P);
     }
+    P.idx.reserve(P.idx.size() + 2 * m);
+    P.val.reserve(P.val.size() + 2 * m);
+    P.ip_key.reserve(P.ip_key.size() + 2 * m);
+    P.ip_val.reserve(P.ip_val.size() + 2 * m);
     for (int64_t k = 0; k < m; ++k) {
+        if (k + kAhead < m) {  // node headers ahead, then the pool lines they point at
+            prefetch_w(&st.node[hs[k + kAhead]]);
+            prefetch_w(&st.node[hd[k + kAhead]]);
+        }
+        if (k + kAhead / 2 < m) {
+            const NodeRec &a = st.node[hs[k + kAhead / 2]], &b = st.node[hd[k + kAhead / 2]];
+            prefetch_w(st.pool.data() + a.off + a.cnt);
+            prefetch_w(st.pool.data() + b.off + b.cnt);
+        }
         append(ctx, hs[k], ((uint32_t)slots[k] << 1) | 0u, P);
         append(ctx, hd[k], ((uint32_t)slots[k] << 1) | 1u, P);
     }
@@ -973,24 +1010,41 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     std::vector<int32_t> slots(m);
     for (int64_t k = 0; k < m; ++k) {
+        if (k + kAhead < m) {
+            const int64_t sa = (int64_t)(hu[k + kAhead] & 0xFFFFFFFFull);
+            if (sa < st.S) prefetch_w(&st.slot[sa]);
+        }
         const uint64_t u = hu[k];
         const int64_t s = (int64_t)(u & 0xFFFFFFFFull);
-        if (u == 0 || s >= st.S || st.uid[s] != u) {
-            for (int64_t j = 0; j < k; ++j) st.uid[slots[j]] = hu[j];
+        if (u == 0 || s >= st.S || st.slot[s].uid != u) {
+            for (int64_t j = 0; j < k; ++j) st.slot[slots[j]].uid = hu[j];
             return fail(ctx, PDG_ENOTFOUND, "uid " + std::to_string(u) + " is not a live edge");
         }
         slots[k] = (int32_t)s;
-        st.uid[s] = 0;  // also catches a uid repeated within the batch
+        st.slot[s].uid = 0;  // also catches a uid repeated within the batch
     }
     Patches P;
     std::vector<int64_t> touched;
     std::vector<uint32_t> recs, hnodes;
     recs.reserve(2 * m);
     hnodes.reserve(2 * m);
+    P.idx.reserve(2 * m);
+    P.val.reserve(2 * m);
+    st.free_stack.reserve(st.free_stack.size() + m);
     for (int64_t k = 0; k < m; ++k) {
+        if (k + kAhead < m) {  // the slot lines were fetched by the validation loop
+            const SlotRec &r = st.slot[slots[k + kAhead]];
+            prefetch_w(&st.node[r.src]);
+            prefetch_w(&st.node[r.dst]);
+        }
+        if (k + kAhead / 2 < m) {
+            const SlotRec &r = st.slot[slots[k + kAhead / 2]];
+            prefetch_w(st.pool.data() + st.node[r.src].off + r.pos0);
+            prefetch_w(st.pool.data() + st.node[r.dst].off + r.pos1);
+        }
         const int32_t s = slots[k];
-        const int32_t a = st.src[s], b = st.dst[s];
-        const uint32_t ia = st.off[a] + st.pos0[s], ib = st.off[b] + st.pos1[s];
+        const int32_t a = st.slot[s].src, b = st.slot[s].dst;
+        const uint32_t ia = st.node[a].off + st.slot[s].pos0, ib = st.node[b].off + st.slot[s].pos1;
         st.pool[ia] = kTomb;
         st.pool[ib] = kTomb;
         P.idx.push_back(ia);
@@ -1001,8 +1055,8 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
         recs.push_back(ib);
         hnodes.push_back((uint32_t)a);
         hnodes.push_back((uint32_t)b);
-        st.nlive[a]--;
-        st.nlive[b]--;
+        st.node[a].nlive--;
+        st.node[b].nlive--;
         st.free_stack.push_back(s);
     }
     st.live -= m;
@@ -1046,7 +1100,7 @@ pdg_status pdg_live_uids(pdg_ctx *ctx, uint64_t *d_uid_out)
     std::vector<uint64_t> out;
     out.reserve(ctx->st.live);
     for (int64_t s = 0; s < ctx->st.hwm; ++s)
-        if (ctx->st.uid[s]) out.push_back(ctx->st.uid[s]);
+        if (ctx->st.slot[s].uid) out.push_back(ctx->st.slot[s].uid);
     if (!out.empty()) {
         PDG_HIP(ctx, hipMemcpyAsync(d_uid_out, out.data(), out.size() * 8, hipMemcpyHostToDevice,
                                     ctx->stream));
@@ -1196,7 +1250,7 @@ pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_
     std::vector<int32_t> slots(m);
     for (int64_t k = 0; k < m; ++k) {
         const int64_t s = (int64_t)(hu[k] & 0xFFFFFFFFull);
-        if (hu[k] == 0 || s >= ctx->st.S || ctx->st.uid[s] != hu[k])
+        if (hu[k] == 0 || s >= ctx->st.S || ctx->st.slot[s].uid != hu[k])
             return fail(ctx, PDG_ENOTFOUND, "uid is not a live edge");
         slots[k] = (int32_t)s;
     }
