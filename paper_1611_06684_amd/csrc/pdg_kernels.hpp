@@ -1,12 +1,16 @@
 // HIP kernels of the primal-dual Gibbs sweep for gfx950 (wave64).
 //
-// Work mapping.  A wave covers P = 64 / LPI items times LPI chains; lane =
-// (item, chain).  Items are edges in the dual phase and node quads (four
-// consecutive nodes) in the primal phase.  With 33 or more chains (LPI = 64)
-// an item owns whole waves, so everything per item -- endpoints, parameter
-// block, incidence segment, dual bit-plane words -- is wave-uniform and comes
-// through scalar loads, and a plane word is directly the lane mask of its
-// chains.
+// Work mapping.  Lanes are chains.  Items are edges in the dual phase and node
+// quads (four consecutive nodes) in the primal phase.  With 33 or more chains
+// (LPI = 64) an item owns whole waves (k_dual64: four edges per wave;
+// k_primal64: one quad per wave), so everything per item -- endpoints,
+// parameter block, incidence segment, mask words -- is wave-uniform and comes
+// through scalar loads or LDS broadcasts, and a mask word is directly the
+// lane mask of its chains.  With 17..32 chains the dual packs two edges per
+// wave and k_primal32 splits one quad's records between the two half-waves;
+// the generic k_dual / k_primal take 64 / LPI items per wave for fewer chains.
+// Hubs (nodes with more than kHubThreshold incidences) are drawn by the hub
+// kernels.
 //
 // Storage (device, all written by this library):
 //   x       uint8  [n][C]                 node states, chain fastest
@@ -260,9 +264,10 @@ __device__ __forceinline__ bool lane_bit(uint64_t mask)
 template <int QM, int LPI, bool UQ>
 __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
 {
+    static_assert(LPI <= 32, "33 or more chains: k_dual64");
     constexpr int D = dim_d(QM);
     constexpr int NCALL = (D + 4) / 5;
-    constexpr int NW = (LPI >= 32) ? 2 * D : 1;      // plane words gathered per wave
+    constexpr int NW = (LPI == 32) ? 2 * D : 1;      // mask words gathered per wave
     constexpr int NREG = (NW + 63) / 64;
     const LaneMap<LPI> lm(g.C);
     const int64_t slot = lm.item;
@@ -320,8 +325,7 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
             // Lanes of absent chains produce bits that nothing reads.
             const uint64_t ya = UQ ? mya[dd / (QM - 1) + 1] : __ballot(xs == a);
             const uint64_t yb = UQ ? myb[dd % (QM - 1) + 1] : __ballot(xd == b);
-            const uint64_t neg = (LPI == 64) ? (0ull - ((sign >> dd) & 1ull))
-                                             : __ballot(((sign >> dd) & 1ull) != 0);
+            const uint64_t neg = __ballot(((sign >> dd) & 1ull) != 0);
             const uint64_t yh = ya ^ neg;
             const uint32_t tp8m1 = thr[2 * dd], tm8 = thr[2 * dd + 1];
             const uint64_t cp = __ballot(W[j] > tp8m1);          // U >= T+
@@ -329,12 +333,7 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
             const uint64_t ch = __ballot(W[j] >= 0x80000000u);   // U >= 2^23
             uint64_t zm = cp | (ch & (yh | yb)) | (cm & yh & yb);
             if (!UQ) zm &= __ballot(dd < De) & mact;
-            if (LPI == 64) {
-                outr[(2 * dd) >> 6] =
-                    pdg_writelane_i32((uint32_t)zm, (2 * dd) & 63, outr[(2 * dd) >> 6]);
-                outr[(2 * dd + 1) >> 6] = pdg_writelane_i32(
-                    (uint32_t)(zm >> 32), (2 * dd + 1) & 63, outr[(2 * dd + 1) >> 6]);
-            } else if (LPI == 32) {
+            if (LPI == 32) {
                 outr[dd >> 6] = pdg_writelane_i32((uint32_t)zm, dd & 63, outr[dd >> 6]);
                 outr[(D + dd) >> 6] =
                     pdg_writelane_i32((uint32_t)(zm >> 32), (D + dd) & 63, outr[(D + dd) >> 6]);
@@ -353,33 +352,16 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
             }
         }
     }
-    // Gathered mask words out to both records, each in its node's orientation:
-    // (a-1)(QM-1) + (b-1) in the src record, (b-1)(QM-1) + (a-1) in the dst
-    // record.  LPI = 64: lane 2d + h holds half h of entry d's mask of this
-    // chain block; LPI = 32: lane p D + d holds item p's word of entry d.
+    // LPI = 32: the gathered mask words go out to both records, each in its
+    // node's orientation: (a-1)(QM-1) + (b-1) in the src record, (b-1)(QM-1) +
+    // (a-1) in the dst record; lane p D + d holds item p's word of entry d.
     auto padded = [&](int dd, int qdv) -> int {
         return (dd / (qdv - 1)) * (QM - 1) + dd % (qdv - 1);
     };
     auto transposed = [&](int dd, int qdv) -> int {
         return (dd % (qdv - 1)) * (QM - 1) + dd / (qdv - 1);
     };
-    if (LPI == 64) {
-        if (live) {
-            uint32_t *z0 = g.rec_z + (r0 * g.CB + lm.cb) * 2 * D;
-            uint32_t *z1 = g.rec_z + (r1 * g.CB + lm.cb) * 2 * D;
-#pragma unroll
-            for (int r = 0; r < NREG; ++r) {
-                const int idx = 64 * r + lm.lane;
-                const int dd = idx >> 1;
-                if (idx < NW && (UQ || dd < De)) {
-                    const int dp = UQ ? dd : padded(dd, qd);
-                    const int dt = transposed(dd, UQ ? QM : qd);
-                    z0[2 * dp + (idx & 1)] = outr[r];
-                    z1[2 * dt + (idx & 1)] = outr[r];
-                }
-            }
-        }
-    } else if (LPI == 32) {
+    if (LPI == 32) {
 #pragma unroll
         for (int r = 0; r < NREG; ++r) {
             const int idx = 64 * r + lm.lane;
@@ -1141,16 +1123,14 @@ __global__ __launch_bounds__(256) void k_hub_finish(Graph g, int64_t nh,
 //   src side c0_row(a) + sum_b 2 theta_ab h_ab, dst side c0_col(b) + sum_a 2 theta_ab |h_ab|;
 // a record is stored in the node's own orientation (row = the node's state),
 // so both sides read the same way; padded entries and tombstones are zero.
-// Then m = max L, weights e^(L(a) - m) (FP32 exp unless EXP64), F cumulative
-// in FP64, x = min{a : u F_{q-1} < F_a} with u = (U + 0.5) 2^-24.
-// With LPI = 64 a mask word pair is the lane mask of the chain block, so an
-// entry costs one select and one FP64 FMA; the quad's records are first
-// touched with vector loads (one pass, all lines in flight together) so the
-// scalar loads of the record walk hit L2.
+// Then the categorical draw of draw_node.  This generic form serves up to 16
+// chains (64 / LPI quads per wave, per-lane record loads); k_primal64 and
+// k_primal32 are the shapes for more chains.
 // ---------------------------------------------------------------------------
 template <int QM, int LPI, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
 {
+    static_assert(LPI <= 16, "33 or more chains: k_primal64; 17..32: k_primal32");
     constexpr int D = dim_d(QM);
     constexpr int RP = rec_len(QM);
     const LaneMap<LPI> lm(g.C);
@@ -1169,118 +1149,37 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
             cnt[j] = g.inc_cnt[quad * 4 + j];
         }
     }
-    const int64_t zstride = (LPI == 64) ? (int64_t)g.CB * D * 2 : (int64_t)D;  // u32 per record
-    uint32_t sink_p = 0, sink_z = 0;
-    if (LPI == 64) {
-        // lane (j, l): line l of node j's rec_p segment and of its rec_z segment
-        const int j = lm.lane >> 4, l = lm.lane & 15;
-        const uint32_t oj = j == 0 ? off[0] : j == 1 ? off[1] : j == 2 ? off[2] : off[3];
-        const uint32_t cj = j == 0 ? cnt[0] : j == 1 ? cnt[1] : j == 2 ? cnt[2] : cnt[3];
-        const uint64_t pb = (uint64_t)oj * (RP * 8), pe = pb + (uint64_t)cj * (RP * 8);
-        const uint64_t pa = (pb & ~(uint64_t)127) + 128 * (uint64_t)l;
-        if (pa < pe)
-            sink_p = *reinterpret_cast<const uint32_t *>(
-                reinterpret_cast<const uint8_t *>(g.rec_p) + pa);
-        const uint64_t zb = (uint64_t)oj * zstride * 4, ze = zb + (uint64_t)cj * zstride * 4;
-        const uint64_t za = (zb & ~(uint64_t)127) + 128 * (uint64_t)l;
-        if (za < ze)
-            sink_z = *reinterpret_cast<const uint32_t *>(
-                reinterpret_cast<const uint8_t *>(g.rec_z) + za);
-    }
     int newx[4], qnv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t node = quad * 4 + j;
-        const bool nvalid = node < g.n;
         newx[j] = -1;
         qnv[j] = 0;
-        if (nvalid) {
-            int &qn = qnv[j];
-            qn = UQ ? QM : (int)g.q[node];
-            // the theta-free part (lam and every c0) is the node's base
-            double L[QM];
+        if (node >= g.n) continue;
+        const int qn = UQ ? QM : (int)g.q[node];
+        qnv[j] = qn;
+        // the theta-free part (lam and every c0) is the node's base
+        double L[QM];
 #pragma unroll
-            for (int a = 0; a < QM; ++a) L[a] = (UQ || a < qn) ? g.base[node * QM + a] : 0.0;
-            const double *hp = g.rec_p + (uint64_t)off[j] * RP;
-            const uint32_t *zp = g.rec_z + (uint64_t)off[j] * zstride +
-                                 ((LPI == 64) ? (uint64_t)lm.cb * D * 2 : 0);
-            auto record = [&](const double *h, const uint32_t *z) {
-                auto theta = [&](int dp) -> bool {
-                    if (LPI == 64) return lane_bit(reinterpret_cast<const uint64_t *>(z)[dp]);
-                    return ((z[dp] >> (lm.c & 31)) & 1u) != 0;
-                };
+        for (int a = 0; a < QM; ++a) L[a] = (UQ || a < qn) ? g.base[node * QM + a] : 0.0;
+        const double *hp = g.rec_p + (uint64_t)off[j] * RP;
+        const uint32_t *zp = g.rec_z + (uint64_t)off[j] * D;
+        for (uint32_t k = 0; k < cnt[j]; ++k, hp += RP, zp += D) {
 #pragma unroll
-                for (int s = 1; s < QM; ++s) {
-                    if (!UQ && s >= qn) break;
-                    double acc = L[s];
+            for (int s = 1; s < QM; ++s) {
+                if (!UQ && s >= qn) break;
+                double acc = L[s];
 #pragma unroll
-                    for (int o = 1; o < QM; ++o) {
-                        // acc + 2 theta h in one FMA: the factor is 0.0 or 2.0
-                        // (a select of inline constants) and 2 h is exact
-                        const int dp = (s - 1) * (QM - 1) + (o - 1);
-                        const double zf = __hiloint2double(theta(dp) ? 0x40000000 : 0, 0);
-                        acc = __builtin_fma(zf, h[dp], acc);
-                    }
-                    L[s] = acc;
+                for (int o = 1; o < QM; ++o) {
+                    // acc + 2 theta h in one FMA: the factor is 0.0 or 2.0 and 2 h is exact
+                    const int dp = (s - 1) * (QM - 1) + (o - 1);
+                    const bool th = ((zp[dp] >> (lm.c & 31)) & 1u) != 0;
+                    acc = __builtin_fma(__hiloint2double(th ? 0x40000000 : 0, 0), hp[dp], acc);
                 }
-            };
-            for (uint32_t k = 0; k < cnt[j]; ++k, hp += RP, zp += zstride) record(hp, zp);
-            double mx = L[0];
-#pragma unroll
-            for (int a = 1; a < QM; ++a)
-                if (UQ || a < qn) mx = fmax(mx, L[a]);
-            double F[QM];
-            double acc = 0.0;
-#pragma unroll
-            for (int a = 0; a < QM; ++a) {
-                if (UQ || a < qn) {
-                    double wgt;
-                    if (EXP64)
-                        wgt = exp(L[a] - mx);
-                    else
-                        wgt = (double)__builtin_amdgcn_exp2f((float)((L[a] - mx) * 1.4426950408889634074));
-                    acc += wgt;
-                }
-                F[a] = acc;
-            }
-            const uint32_t U = Wn[j] >> 8;
-            const double target = ((double)U + 0.5) * 5.9604644775390625e-08 * F[QM - 1];
-            int xn = qn - 1;
-#pragma unroll
-            for (int a = QM - 1; a >= 0; --a)
-                if ((UQ || a < qn) && target < F[a]) xn = a;
-            newx[j] = xn;
-        }
-    }
-    // the touch loads end here (their values are not used)
-    asm volatile("" ::"v"(sink_p), "v"(sink_z));
-    if (LPI == 64 && count && g.CB == 1) {
-        // The wave owns the quad's counters (the array is padded to whole
-        // quads): scalar-load them before any store, then store each node's
-        // row with one vector store (lane a holds state a).
-        uint32_t row[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool nvalid = quad * 4 + j < g.n;
-            row[j] = 0u;
-#pragma unroll
-            for (int a = 0; a < QM; ++a) {
-                const uint32_t v = g.counts[(quad * 4 + j) * QM + a] +
-                                   (uint32_t)__popcll(__ballot(nvalid && cvalid && newx[j] == a));
-                if (lm.lane == a) row[j] = v;
+                L[s] = acc;
             }
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t node = quad * 4 + j;
-            if (node < g.n && cvalid) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t node = quad * 4 + j;
-            if (node < g.n && lm.lane < qnv[j]) g.counts[node * QM + lm.lane] = row[j];
-        }
-        return;
+        newx[j] = draw_node<QM, UQ, EXP64>(L, qn, Wn[j] >> 8);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -1289,21 +1188,15 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
         const bool active = nvalid && cvalid;
         if (active) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
         if (count) {
+            // one chain block: the lane group of the quad owns the node's counters
             const bool leader = nvalid && (lm.lane % LPI == 0);
+            const int p0 = (lm.lane / LPI) * LPI;
 #pragma unroll
             for (int a = 0; a < QM; ++a) {
-                const uint64_t bal = __ballot(active && newx[j] == a);
-                uint64_t mine = bal;
-                if (LPI < 64) {
-                    const int p0 = (lm.lane / LPI) * LPI;
-                    mine = (bal >> p0) & ((LPI >= 64) ? ~0ull : ((1ull << (LPI & 63)) - 1ull));
-                }
-                if (leader && a < qnv[j] && mine != 0) {
-                    if (g.CB == 1)  // this wave owns the node: no other writer
-                        g.counts[node * QM + a] += (uint32_t)__popcll(mine);
-                    else
-                        atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(mine));
-                }
+                const uint64_t mine =
+                    (__ballot(active && newx[j] == a) >> p0) & ((1ull << LPI) - 1ull);
+                if (leader && a < qnv[j] && mine != 0)
+                    g.counts[node * QM + a] += (uint32_t)__popcll(mine);
             }
         }
     }
