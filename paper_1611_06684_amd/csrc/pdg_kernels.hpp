@@ -251,6 +251,33 @@ __device__ __forceinline__ bool lane_bit(uint64_t mask)
     return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
 
+// Marginal counters of a node quad whose wave owns them (one chain block):
+// the 4 QM counters are contiguous (the array is padded to whole quads), so
+// they are scalar-loaded (before any store of the kernel), raised by the
+// popcounts of the state ballots, gathered into lanes j QM + a and written by
+// one vector store.  `drawn` bit j: node j was drawn by this wave (qn[j] states);
+// `chain` is this lane's chain predicate.
+template <int QM>
+__device__ __forceinline__ void count_quad(uint32_t *__restrict__ counts, int64_t quad,
+                                           const int (&newx)[4], const int (&qn)[4],
+                                           uint32_t drawn, bool chain, int lane)
+{
+    uint32_t *cq = counts + quad * 4 * QM;
+    uint32_t row = 0;
+    uint64_t wmask = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int a = 0; a < QM; ++a) {
+            const uint32_t add =
+                (uint32_t)__popcll(__ballot(((drawn >> j) & 1u) && chain && newx[j] == a));
+            row = pdg_writelane_i32(cq[j * QM + a] + add, j * QM + a, row);
+        }
+        if ((drawn >> j) & 1u) wmask |= ((1ull << qn[j]) - 1ull) << (j * QM);
+    }
+    if (lane_bit(wmask)) cq[lane] = row;
+}
+
 // ---------------------------------------------------------------------------
 // a3: dual phase.  Every live edge, chain and entry d = (a-1)(q_dst-1)+(b-1):
 // theta = [U >= T(k)], U from call (uid, DUAL, 16 c + d / 5, t), value d mod 5.
@@ -711,30 +738,14 @@ __global__ __launch_bounds__(256) void k_primal64(Graph g, uint32_t t, int count
     // the touch loads end here (their values are not used)
     asm volatile("" ::"v"(sink_z), "v"(sink_b));
     if (count && g.CB == 1) {
-        // The wave owns the quad's counters (the array is padded to whole
-        // quads): scalar-load them before any store, then store each node's
-        // row with one vector store (lane a holds state a).
-        uint32_t row[4];
+        uint32_t drawn = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool nvalid = quad * 4 + j < g.n;
-            row[j] = 0u;
-#pragma unroll
-            for (int a = 0; a < QM; ++a) {
-                const uint32_t v = g.counts[(quad * 4 + j) * QM + a] +
-                                   (uint32_t)__popcll(__ballot(nvalid && cvalid && newx[j] == a));
-                if (lane == a) row[j] = v;
-            }
-        }
+        for (int j = 0; j < 4; ++j) drawn |= (qnv[j] > 0 ? 1u : 0u) << j;
+        count_quad<QM>(g.counts, quad, newx, qnv, drawn, cvalid, lane);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t node = quad * 4 + j;
             if (newx[j] >= 0 && cvalid) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t node = quad * 4 + j;
-            if (node < g.n && lane < qnv[j]) g.counts[node * QM + lane] = row[j];
         }
         return;
     }
@@ -933,28 +944,15 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
         qnv[jj] = newx[jj] >= 0 ? (UQ ? QM : (int)g.q[quad * 4 + jj]) : 0;
     const bool writer = p == 0 && cvalid;
     if (count) {
-        // the wave owns the quad's counters (one chain block; padded to whole quads)
-        uint32_t row[4];
+        // the wave owns the quad's counters (one chain block)
+        uint32_t drawn = 0;
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const bool nvalid = quad * 4 + jj < g.n;
-            row[jj] = 0u;
-#pragma unroll
-            for (int a = 0; a < QM; ++a) {
-                const uint32_t v = g.counts[(quad * 4 + jj) * QM + a] +
-                                   (uint32_t)__popcll(__ballot(nvalid && writer && newx[jj] == a));
-                if (lane == a) row[jj] = v;
-            }
-        }
+        for (int jj = 0; jj < 4; ++jj) drawn |= (qnv[jj] > 0 ? 1u : 0u) << jj;
+        count_quad<QM>(g.counts, quad, newx, qnv, drawn, writer, lane);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const int64_t node = quad * 4 + jj;
             if (newx[jj] >= 0 && writer) g.x[node * g.C + c] = (uint8_t)newx[jj];
-        }
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int64_t node = quad * 4 + jj;
-            if (lane < qnv[jj]) g.counts[node * QM + lane] = row[jj];
         }
         return;
     }
