@@ -303,6 +303,31 @@ def test_edits_then_teacher_forced():
     s.close()
 
 
+def test_checkpoint_resume_is_bit_exact():
+    """A chain saved after t1 sweeps (state and sweep counter) and resumed in a
+    fresh context continues exactly as the uninterrupted run: the generator is
+    counter-based, so (x, t) is the whole state of a chain."""
+    for model, C in [(W.table_grid(40, 30, 4, seed=21), 64), (W.chung_lu(2048, 5, seed=22), 32)]:
+        seed, t1, t2 = 11, 3, 4
+        a = _sampler(model, C, seed)
+        a.init()
+        a.sweep(t1 + t2)
+        x_full = a.state().cpu().numpy()
+        a.close()
+        b = _sampler(model, C, seed)
+        b.init()
+        b.sweep(t1)
+        x_mid, t_mid = b.state().clone(), b.t
+        b.close()
+        c = _sampler(model, C, seed)
+        c.set_state(x_mid)
+        c.t = t_mid
+        c.sweep(t2)
+        assert c.t == t1 + t2
+        assert np.array_equal(c.state().cpu().numpy(), x_full)
+        c.close()
+
+
 def test_error_paths():
     import torch
     from paper_1611_06684_amd import pdg
