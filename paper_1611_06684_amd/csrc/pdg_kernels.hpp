@@ -615,10 +615,10 @@ __device__ __forceinline__ int draw_node(const double (&L)[QM], int qn, uint32_t
 // wait, after their lines were touched into L2.  A node with more records
 // than a staged chunk holds is walked chunk by chunk.
 // ---------------------------------------------------------------------------
-// eight waves per SIMD: the kernel waits on memory, and the register budget
-// of eight waves costs it no spills
+// eight waves per SIMD where the register budget of eight waves costs no
+// spills (q_max <= 5): the kernel waits on memory
 template <int QM, bool UQ, bool EXP64>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_primal64(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QM <= 5 ? 8 : 1))) void k_primal64(
     Graph g, uint32_t t, int count)
 {
     constexpr int D = dim_d(QM);
