@@ -77,6 +77,9 @@ def _models():
     yield "grid_16x16_q2_f32_C100", W.table_grid(16, 16, 2, seed=5, pair_std=1.0), 100
     yield "ising_10x10_f64_C13", W.ising_grid(10, 10, seed=6, J_half_range=0.8), 13
     yield "chung_lu_4096_q8_f32_C32", W.chung_lu(4096, 8, seed=7), 32
+    # 33+ chains with large q_max: two-load LDS staging, mixed and uniform q
+    yield "random_mixed_q678_f32_C40", W.random_graph(400, 1600, [6, 7, 8], seed=11, dtype="f32"), 40
+    yield "grid_18x17_q6_f64_C64", W.table_grid(18, 17, 6, seed=12, dtype="f64"), 64
     # hubs: nodes with more incidences than a quad kernel takes (split into pieces)
     yield "hubs_q4_f32_C64", _hub_graph(900, [4], 3, 8), 64
     yield "hubs_mixed_q235_f32_C32", _hub_graph(700, [2, 3, 5], 4, 9), 32
