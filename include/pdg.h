@@ -79,14 +79,18 @@ pdg_status pdg_set_nodes(pdg_ctx *ctx, int64_t n, const int32_t *d_q, const void
 /* Insert m edges between sweeps (Sec. 4.2 decomposition runs on the new
  * edges).  d_src, d_dst: int32 [m] (src != dst, both < n); d_log_phi:
  * [m][q_max][q_max] log phi_e(a, b), row a = state of src.  d_uid_out:
- * uint64 [m] receives the library-issued uids (never reused).  O(m) work:
- * no colouring, no rebuild of the incidence lists.  The call synchronizes the
- * stream (slot and segment allocation is decided on the host). */
+ * uint64 [m] receives the library-issued uids (never reused).  O(m) work on
+ * the device: no colouring, no rebuild of the incidence lists; the new entries
+ * of a node follow its old ones in batch order.  Nothing changes when an
+ * endpoint is out of range or equal to the other (PDG_EINVAL), a table entry
+ * is not finite (PDG_ENONPOS) or capacity is short (PDG_ECAPACITY).  The call
+ * synchronizes the stream (it reads back a few counters to size launches). */
 pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const int32_t *d_dst,
                             const void *d_log_phi, uint64_t *d_uid_out);
 
-/* Remove m live edges by uid between sweeps.  Nothing is removed if any uid
- * is unknown or repeated (PDG_ENOTFOUND).  Synchronizes the stream. */
+/* Remove m live edges by uid between sweeps (O(m) work on the device; the
+ * freed slots are reused by later inserts under new uids).  Nothing is removed
+ * if any uid is unknown or repeated (PDG_ENOTFOUND).  Synchronizes the stream. */
 pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid);
 
 /* Number of live edges, and their uids in slot order (d_uid_out: uint64 [live]). */

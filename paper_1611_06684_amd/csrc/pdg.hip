@@ -1,13 +1,13 @@
 // libpdg: host runtime and C ABI of the primal-dual Gibbs sweep (include/pdg.h).
 //
 // The context owns every device buffer.  Sweeps are two kernels per sweep on
-// the caller's stream.  Edge edits are decided on the host -- a slot
-// allocator (free stack, generation-tagged uids) and per-node incidence
-// segments with slack -- and written to the device by small scatter kernels,
-// so an edit batch costs O(batch) plus an occasional segment relocation; no
-// colouring and no rebuild of the incidence lists is ever needed (the
-// abstract, Sec. 1 and Sec. 6 of the paper motivate the method by exactly
-// this setting).
+// the caller's stream.  Edge edits run as kernels too (pdg_store.hpp): a
+// device free-slot stack with generation-tagged uids and per-node incidence
+// segments with slack, so an edit batch costs O(batch) plus an occasional
+// segment relocation; no colouring and no rebuild of the incidence lists is
+// ever needed (the abstract, Sec. 1 and Sec. 6 of the paper motivate the
+// method by exactly this setting).  The host only reads back a few counters
+// (EditSummary) to size launches and report errors.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,35 +17,15 @@
 #include <string>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "pdg.h"
 #include "pdg_kernels.hpp"
+#include "pdg_store.hpp"
 
 namespace pdg {
 
 static thread_local std::string g_global_err;
-
-// Host mirror of the edge store, laid out so that an edit touches one cache
-// line per slot and one per node.
-struct SlotRec {
-    uint64_t uid;        // 0 = free
-    int32_t src, dst;
-    uint32_t pos0, pos1; // position of the slot's entry in its src / dst segment
-    uint32_t gen;        // generation of the slot (high word of its uids)
-    uint32_t pad;
-};
-struct NodeRec {
-    uint32_t off, cnt, cap, nlive;  // segment [off, off + cnt) of cap entries, live ones
-};
-struct Store {
-    int64_t S = 0;
-    std::vector<SlotRec> slot;    // [S]
-    std::vector<int32_t> free_stack;
-    int64_t hwm = 0, live = 0;
-    std::vector<NodeRec> node;    // [n]
-    std::vector<uint32_t> mark;                  // per node, zero between calls (edit scratch)
-    std::vector<uint32_t> pool;
-    int64_t pool_top = 0;
-};
 
 }  // namespace pdg
 
@@ -79,6 +59,16 @@ struct pdg_ctx {
     double *d_rec_p = nullptr;
     uint32_t *d_rec_z = nullptr;
     int64_t dev_pool_cap = 0;
+    // edge store (device side in pdg_store.hpp; the host keeps these scalars)
+    int64_t S = 0;         // edge slots
+    int64_t ftop = 0;      // height of the free-slot stack
+    int64_t live = 0;      // live edges
+    int64_t hwm = 0;       // slots [0, hwm) may be live
+    int64_t pool_top = 0;  // first pool entry no segment uses
+    int32_t *d_free = nullptr;
+    uint32_t *d_gen = nullptr, *d_claim = nullptr;
+    uint32_t *d_cap = nullptr, *d_nlive = nullptr, *d_mark = nullptr;
+    pdg::EditSummary *d_sum = nullptr;
     uint32_t *d_flag = nullptr;
     void *d_scratch = nullptr;
     int64_t scratch_bytes = 0;
@@ -90,7 +80,6 @@ struct pdg_ctx {
     int64_t hub_cap = 0;         // u32 capacity of d_hub
     double *d_part = nullptr;    // [np][CB][QM - 1][64]
     int64_t part_cap = 0;        // doubles
-    pdg::Store st;
     std::string err;
 };
 
@@ -200,7 +189,7 @@ static Graph make_graph(pdg_ctx *ctx)
     g.x = ctx->d_x;
     g.counts = ctx->d_counts;
     g.n = ctx->n;
-    g.hwm = ctx->st.hwm;
+    g.hwm = ctx->hwm;
     g.C = ctx->C;
     g.CB = (int32_t)cdiv(ctx->C, 64);
     g.heavy = ctx->hub_thr;
@@ -372,284 +361,179 @@ static void launch_decompose(int qm, bool f64, int64_t m, const int32_t *qs, con
     }
 }
 
-// Finite-entry check of an edit batch before anything is changed.
-template <int QM, typename T>
-__global__ void k_check_tables(int64_t m, const int32_t *__restrict__ src,
-                               const int32_t *__restrict__ dst, const uint8_t *__restrict__ q,
-                               const T *__restrict__ phi, uint32_t *__restrict__ bad)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    const int qs = q[src[k]], qd = q[dst[k]];
-    const T *L = phi + k * QM * QM;
-    for (int a = 0; a < qs; ++a)
-        for (int b = 0; b < qd; ++b)
-            if (!isfinite((double)L[a * QM + b])) atomicOr(bad, 1u);
-}
-
+// Check of an insert batch before anything changes (k_check_insert).
 template <int QM>
-static void check_q(bool f64, int64_t m, const int32_t *s, const int32_t *d, const uint8_t *q,
-                    const void *phi, uint32_t *bad, hipStream_t st)
+static void check_insert_q(pdg_ctx *ctx, int64_t m, const int32_t *s, const int32_t *d,
+                           const void *phi)
 {
-    if (f64)
-        k_check_tables<QM, double><<<grid_for(m), 256, 0, st>>>(m, s, d, q,
-                                                               static_cast<const double *>(phi), bad);
+    if (ctx->cfg.precision == PDG_PRECISION_F64)
+        k_check_insert<QM, double><<<grid_for(m), 256, 0, ctx->stream>>>(
+            m, s, d, ctx->n, ctx->d_q, static_cast<const double *>(phi), ctx->d_free, ctx->ftop,
+            ctx->d_gen, ctx->d_sum);
     else
-        k_check_tables<QM, float><<<grid_for(m), 256, 0, st>>>(m, s, d, q,
-                                                              static_cast<const float *>(phi), bad);
+        k_check_insert<QM, float><<<grid_for(m), 256, 0, ctx->stream>>>(
+            m, s, d, ctx->n, ctx->d_q, static_cast<const float *>(phi), ctx->d_free, ctx->ftop,
+            ctx->d_gen, ctx->d_sum);
 }
 
-static void launch_check(int qm, bool f64, int64_t m, const int32_t *s, const int32_t *d,
-                         const uint8_t *q, const void *phi, uint32_t *bad, hipStream_t st)
+static void launch_check_insert(pdg_ctx *ctx, int64_t m, const int32_t *s, const int32_t *d,
+                                const void *phi)
 {
-    switch (qm) {
-    case 2: check_q<2>(f64, m, s, d, q, phi, bad, st); break;
-    case 3: check_q<3>(f64, m, s, d, q, phi, bad, st); break;
-    case 4: check_q<4>(f64, m, s, d, q, phi, bad, st); break;
-    case 5: check_q<5>(f64, m, s, d, q, phi, bad, st); break;
-    case 6: check_q<6>(f64, m, s, d, q, phi, bad, st); break;
-    case 7: check_q<7>(f64, m, s, d, q, phi, bad, st); break;
-    default: check_q<8>(f64, m, s, d, q, phi, bad, st); break;
+    switch (ctx->QM) {
+    case 2: check_insert_q<2>(ctx, m, s, d, phi); break;
+    case 3: check_insert_q<3>(ctx, m, s, d, phi); break;
+    case 4: check_insert_q<4>(ctx, m, s, d, phi); break;
+    case 5: check_insert_q<5>(ctx, m, s, d, phi); break;
+    case 6: check_insert_q<6>(ctx, m, s, d, phi); break;
+    case 7: check_insert_q<7>(ctx, m, s, d, phi); break;
+    default: check_insert_q<8>(ctx, m, s, d, phi); break;
     }
 }
 
 // ---------------------------------------------------------------- edge store
-static uint32_t slack_for(uint32_t k) { return std::max<uint32_t>(2u, k / 4u); }
+static int64_t a256(int64_t bytes) { return (bytes + 255) / 256 * 256; }
 
-// Edits touch the host mirror at random places; the loops below request the
-// lines of later iterations ahead of time (distance kAhead).
-constexpr int64_t kAhead = 16;
-template <typename T>
-static inline void prefetch_w(const T *p)
-{
-    __builtin_prefetch(p, 1, 0);
-}
-
-struct Patches {
-    std::vector<uint32_t> idx, val;        // pool entries
-    bool full = false;                     // whole pool and every header re-laid
-    std::vector<uint32_t> mv_from, mv_to;  // incidence records that moved
-    std::vector<uint32_t> ip_key, ip_val;  // ipos[2 slot + side] = record index
+// Consecutive 256-byte aligned pieces of one scratch buffer.
+struct Carve {
+    char *p;
+    template <typename T>
+    T *take(int64_t count)
+    {
+        T *r = reinterpret_cast<T *>(p);
+        p += a256(std::max<int64_t>(count, 1) * (int64_t)sizeof(T));
+        return r;
+    }
+    template <typename T>
+    static int64_t size(int64_t count)
+    {
+        return a256(std::max<int64_t>(count, 1) * (int64_t)sizeof(T));
+    }
 };
 
-static void note_entry(Store &st, uint32_t e, uint32_t w, uint32_t rec, Patches &P)
+static pdg_status read_sum(pdg_ctx *ctx, EditSummary *h)
 {
-    const uint32_t slot = e >> 1;
-    if (e & 1u)
-        st.slot[slot].pos1 = w;
-    else
-        st.slot[slot].pos0 = w;
-    P.ip_key.push_back(2u * slot + (e & 1u));
-    P.ip_val.push_back(rec);
-}
-
-// Lay every node's live entries out again, leaving room for `need` appends.
-static pdg_status full_compact(pdg_ctx *ctx, const std::vector<uint32_t> &need, Patches &P)
-{
-    Store &st = ctx->st;
-    const int64_t n = ctx->n;
-    std::vector<uint32_t> noff(n), ncap(n);
-    uint64_t total = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        const uint32_t want = st.node[i].nlive + need[i];
-        ncap[i] = want ? want + slack_for(want) : 0;
-        noff[i] = (uint32_t)total;
-        total += ncap[i];
-    }
-    const uint64_t size = total + total / 4 + 1024;
-    if (size >= 0xFFFFFFF0ull) return fail(ctx, PDG_ECAPACITY, "incidence pool exceeds 2^32 entries");
-    std::vector<uint32_t> npool((size_t)size, kTomb);
-    P.full = true;
-    P.idx.clear();
-    P.val.clear();
-    P.mv_from.clear();
-    P.mv_to.clear();
-    for (int64_t i = 0; i < n; ++i) {
-        uint32_t w = 0;
-        for (uint32_t k = 0; k < st.node[i].cnt; ++k) {
-            const uint32_t e = st.pool[st.node[i].off + k];
-            if (e == kTomb) continue;
-            npool[noff[i] + w] = e;
-            P.mv_from.push_back(st.node[i].off + k);
-            P.mv_to.push_back(noff[i] + w);
-            note_entry(st, e, w, noff[i] + w, P);
-            ++w;
-        }
-        st.node[i].off = noff[i];
-        st.node[i].cnt = w;
-        st.node[i].cap = ncap[i];
-    }
-    st.pool.swap(npool);
-    st.pool_top = (int64_t)total;
-    return PDG_OK;
-}
-
-static void relocate(pdg_ctx *ctx, int64_t i, uint32_t need, Patches &P)
-{
-    Store &st = ctx->st;
-    const uint32_t want = st.node[i].nlive + need;
-    const uint32_t ncap = want + slack_for(want);
-    const uint32_t noff = (uint32_t)st.pool_top;
-    st.pool_top += ncap;
-    uint32_t w = 0;
-    for (uint32_t k = 0; k < st.node[i].cnt; ++k) {
-        const uint32_t e = st.pool[st.node[i].off + k];
-        if (e == kTomb) continue;
-        st.pool[noff + w] = e;
-        P.idx.push_back(noff + w);
-        P.val.push_back(e);
-        P.mv_from.push_back(st.node[i].off + k);
-        P.mv_to.push_back(noff + w);
-        note_entry(st, e, w, noff + w, P);
-        ++w;
-    }
-    st.node[i].off = noff;
-    st.node[i].cnt = w;
-    st.node[i].cap = ncap;
-}
-
-static void append(pdg_ctx *ctx, int64_t i, uint32_t e, Patches &P)
-{
-    Store &st = ctx->st;
-    const uint32_t p = st.node[i].cnt++;
-    st.pool[st.node[i].off + p] = e;
-    if (!P.full) {
-        P.idx.push_back(st.node[i].off + p);
-        P.val.push_back(e);
-    }
-    note_entry(st, e, p, st.node[i].off + p, P);
-    st.node[i].nlive++;
-}
-
-// Upload a host vector to a fresh region of the scratch buffer.
-template <typename T>
-static T *stage(pdg_ctx *ctx, char *&cursor, const std::vector<T> &v)
-{
-    T *p = reinterpret_cast<T *>(cursor);
-    if (!v.empty())
-        (void)hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream);
-    cursor += ((v.size() * sizeof(T) + 255) / 256) * 256;
-    return p;
-}
-
-// Push host-side changes of the incidence structure and its records to the
-// device: record moves (into new buffers after a full re-layout), pool
-// entries, segment headers and ipos.
-static pdg_status upload(pdg_ctx *ctx, Patches &P, const std::vector<int64_t> &touched)
-{
-    Store &st = ctx->st;
-    const int64_t nmv = (int64_t)P.mv_from.size();
-    const int64_t np = (int64_t)P.idx.size();
-    const int64_t nn = (int64_t)touched.size();
-    const int64_t nip = (int64_t)P.ip_key.size();
-    std::vector<uint32_t> hn(nn), ho(nn), hc(nn);
-    for (int64_t k = 0; k < nn; ++k) {
-        hn[k] = (uint32_t)touched[k];
-        ho[k] = st.node[touched[k]].off;
-        hc[k] = st.node[touched[k]].cnt;
-    }
-    void *s;
-    PDG_TRY(scratch(ctx, 4 * (2 * nmv + 2 * np + 3 * nn + 2 * nip) + 8 * 256, &s));
-    char *cur = static_cast<char *>(s);
-    uint32_t *dmf = stage(ctx, cur, P.mv_from), *dmt = stage(ctx, cur, P.mv_to);
-    uint32_t *di = stage(ctx, cur, P.idx), *dv = stage(ctx, cur, P.val);
-    uint32_t *dn = stage(ctx, cur, hn), *dof = stage(ctx, cur, ho), *dc = stage(ctx, cur, hc);
-    uint32_t *dk = stage(ctx, cur, P.ip_key), *dkv = stage(ctx, cur, P.ip_val);
     PDG_HIP(ctx, hipGetLastError());
-    if (P.full) {
-        // new pool, records moved into fresh buffers
-        const int64_t cap = (int64_t)st.pool.size();
-        uint32_t *npool = nullptr;
-        double *nrp = nullptr;
-        uint32_t *nrz = nullptr;
-        PDG_TRY(dalloc(ctx, (void **)&npool, cap * 4));
-        // the primal stages records in 16-byte pieces: pad past the last one
-        pdg_status a = dalloc(ctx, (void **)&nrp, cap * ctx->RP * 8 + 256);
-        if (a == PDG_OK) a = dalloc(ctx, (void **)&nrz, cap * ctx->ZW * 4 + 256);
-        if (a != PDG_OK) {
-            (void)hipFree(npool);
-            if (nrp) (void)hipFree(nrp);
-            return a;
-        }
-        PDG_HIP(ctx, hipMemsetAsync(nrp, 0, cap * ctx->RP * 8 + 256, ctx->stream));
-        PDG_HIP(ctx, hipMemsetAsync(nrz, 0, cap * ctx->ZW * 4 + 256, ctx->stream));
-        if (nmv && ctx->d_rec_p) {
-            k_move_rec_p<<<grid_for(nmv * ctx->RP), 256, 0, ctx->stream>>>(nmv, ctx->RP, dmf, dmt,
-                                                                          ctx->d_rec_p, nrp);
-            k_move_rec_z<<<grid_for(nmv * ctx->ZW), 256, 0, ctx->stream>>>(nmv, ctx->ZW, dmf, dmt,
-                                                                          ctx->d_rec_z, nrz);
-            PDG_HIP(ctx, hipGetLastError());
-        }
-        PDG_HIP(ctx, hipMemcpyAsync(npool, st.pool.data(), cap * 4, hipMemcpyHostToDevice,
-                                    ctx->stream));
-        std::vector<uint32_t> all_off((size_t)ctx->n), all_cnt((size_t)ctx->n);
-        for (int64_t i = 0; i < ctx->n; ++i) {
-            all_off[i] = st.node[i].off;
-            all_cnt[i] = st.node[i].cnt;
-        }
-        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_off, all_off.data(), (size_t)ctx->n * 4,
-                                    hipMemcpyHostToDevice, ctx->stream));
-        PDG_HIP(ctx, hipMemcpyAsync(ctx->d_cnt, all_cnt.data(), (size_t)ctx->n * 4,
-                                    hipMemcpyHostToDevice, ctx->stream));
-        PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        if (ctx->d_pool) PDG_HIP(ctx, hipFree(ctx->d_pool));
-        if (ctx->d_rec_p) PDG_HIP(ctx, hipFree(ctx->d_rec_p));
-        if (ctx->d_rec_z) PDG_HIP(ctx, hipFree(ctx->d_rec_z));
-        ctx->d_pool = npool;
-        ctx->d_rec_p = nrp;
-        ctx->d_rec_z = nrz;
-        ctx->dev_pool_cap = cap;
-    } else {
-        if (st.pool_top > ctx->dev_pool_cap)
-            return fail(ctx, PDG_EINVAL, "internal: pool beyond device capacity without re-layout");
-        if (nmv) {  // relocated segments land in unused pool space: no overlap
-            k_move_rec_p<<<grid_for(nmv * ctx->RP), 256, 0, ctx->stream>>>(
-                nmv, ctx->RP, dmf, dmt, ctx->d_rec_p, ctx->d_rec_p);
-            k_move_rec_z<<<grid_for(nmv * ctx->ZW), 256, 0, ctx->stream>>>(
-                nmv, ctx->ZW, dmf, dmt, ctx->d_rec_z, ctx->d_rec_z);
-        }
-        if (np) k_scatter_u32<<<grid_for(np), 256, 0, ctx->stream>>>(np, di, dv, ctx->d_pool);
-        if (nn)
-            k_scatter_nodes<<<grid_for(nn), 256, 0, ctx->stream>>>(nn, dn, dof, dc, ctx->d_off,
-                                                                   ctx->d_cnt);
-        PDG_HIP(ctx, hipGetLastError());
-    }
-    if (nip) {
-        k_set_ipos<<<grid_for(nip), 256, 0, ctx->stream>>>(nip, dk, dkv, ctx->d_ipos);
-        PDG_HIP(ctx, hipGetLastError());
-    }
+    PDG_HIP(ctx, hipMemcpyAsync(h, ctx->d_sum, sizeof(EditSummary), hipMemcpyDeviceToHost,
+                                ctx->stream));
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PDG_OK;
 }
 
-template <int QM>
-static void node_base_q(pdg_ctx *ctx, int64_t nn, const uint32_t *dnodes)
+static pdg_status reset_sum(pdg_ctx *ctx)
 {
-    k_node_base<QM><<<grid_for(nn * 64), 256, 0, ctx->stream>>>(
-        nn, dnodes, ctx->d_lam, ctx->d_off, ctx->d_cnt, ctx->d_pool, ctx->d_params, ctx->d_base);
+    k_sum_reset<<<1, 64, 0, ctx->stream>>>(ctx->d_sum);
+    PDG_HIP(ctx, hipGetLastError());
+    return PDG_OK;
 }
 
-// base of the listed nodes (after their incidence lists changed)
-static void launch_node_base(pdg_ctx *ctx, int64_t nn, const uint32_t *dnodes)
+// Bits of a node id (radix sort keys).
+static int key_bits(int64_t n)
+{
+    int b = 1;
+    while (b < 32 && (1ll << b) < n) ++b;
+    return b;
+}
+
+// Temporary storage of the library primitives used by the edit path.
+static size_t prim_bytes(int64_t m2, int64_t n)
+{
+    size_t a = 0, b = 0, c = 0, d = 0, e = 0, f = 0;
+    const uint32_t *k = nullptr;
+    uint32_t *o = nullptr;
+    const uint64_t *k64 = nullptr;
+    uint64_t *o64 = nullptr;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, a, k, o, k, o, (int)m2, 0, 32);
+    (void)hipcub::DeviceRunLengthEncode::Encode(nullptr, b, k, o, o, o, (int)m2);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, c, k, o, (int)m2);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, d, k64, o64, (int)m2);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, e, k64, o64, (int)n);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, f, k, o, (int)n);
+    return std::max({a, b, c, d, e, f, (size_t)256});
+}
+
+template <int QM>
+static void node_base_q(pdg_ctx *ctx, int64_t nn, const uint32_t *count, const uint32_t *dnodes)
+{
+    k_node_base<QM><<<grid_for(nn * 64), 256, 0, ctx->stream>>>(
+        nn, count, dnodes, ctx->d_lam, ctx->d_off, ctx->d_cnt, ctx->d_pool, ctx->d_params,
+        ctx->d_base);
+}
+
+// base of the listed nodes (after their incidence lists changed); with
+// `count`, only the first *count of the nn listed.
+static void launch_node_base(pdg_ctx *ctx, int64_t nn, const uint32_t *count,
+                             const uint32_t *dnodes)
 {
     if (nn == 0) return;
     switch (ctx->QM) {
-    case 2: node_base_q<2>(ctx, nn, dnodes); break;
-    case 3: node_base_q<3>(ctx, nn, dnodes); break;
-    case 4: node_base_q<4>(ctx, nn, dnodes); break;
-    case 5: node_base_q<5>(ctx, nn, dnodes); break;
-    case 6: node_base_q<6>(ctx, nn, dnodes); break;
-    case 7: node_base_q<7>(ctx, nn, dnodes); break;
-    default: node_base_q<8>(ctx, nn, dnodes); break;
+    case 2: node_base_q<2>(ctx, nn, count, dnodes); break;
+    case 3: node_base_q<3>(ctx, nn, count, dnodes); break;
+    case 4: node_base_q<4>(ctx, nn, count, dnodes); break;
+    case 5: node_base_q<5>(ctx, nn, count, dnodes); break;
+    case 6: node_base_q<6>(ctx, nn, count, dnodes); break;
+    case 7: node_base_q<7>(ctx, nn, count, dnodes); break;
+    default: node_base_q<8>(ctx, nn, count, dnodes); break;
     }
 }
 
-// Hub list and piece table from the host's segment counts (the device holds
-// the same counts).  Hubs are split only with 32 or more chains and while a
-// hub piece kernel's LDS chunk holds at least the records of one step.
-static pdg_status rebuild_hubs(pdg_ctx *ctx)
+// Lay every segment out again in fresh buffers, with room for the batch's
+// appends (runlen of the distinct nodes uniq), and free the old buffers.
+// ncap / noff: scratch of n entries.
+static pdg_status full_relayout(pdg_ctx *ctx, int64_t runs, const uint32_t *uniq,
+                                const uint32_t *runlen, uint64_t *ncap, uint64_t *noff, void *tmp,
+                                size_t tb)
 {
-    Store &st = ctx->st;
+    const int64_t n = ctx->n;
+    const hipStream_t st = ctx->stream;
+    k_scatter_runs<<<grid_for(runs), 256, 0, st>>>(runs, &ctx->d_sum->runs, uniq, runlen,
+                                                   ctx->d_mark);
+    k_full_cap<<<grid_for(n), 256, 0, st>>>(n, ctx->d_nlive, ctx->d_mark, ncap);
+    PDG_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp, tb, ncap, noff, (int)n, st));
+    k_scan_total<<<1, 64, 0, st>>>(n, ncap, noff, &ctx->d_sum->total);
+    k_unmark<<<grid_for(runs), 256, 0, st>>>(runs, &ctx->d_sum->runs, uniq, ctx->d_mark);
+    EditSummary h;
+    PDG_TRY(read_sum(ctx, &h));
+    const uint64_t total = h.total, size = total + total / 4 + 1024;
+    if (size >= 0xFFFFFFF0ull) return fail(ctx, PDG_ECAPACITY, "incidence pool exceeds 2^32 entries");
+    const int64_t cap = (int64_t)size;
+    uint32_t *npool = nullptr;
+    double *nrp = nullptr;
+    uint32_t *nrz = nullptr;
+    PDG_TRY(dalloc(ctx, (void **)&npool, cap * 4));
+    // the primal stages records in 16-byte pieces: pad past the last one
+    pdg_status a = dalloc(ctx, (void **)&nrp, cap * ctx->RP * 8 + 256);
+    if (a == PDG_OK) a = dalloc(ctx, (void **)&nrz, cap * ctx->ZW * 4 + 256);
+    if (a != PDG_OK) {
+        (void)hipFree(npool);
+        if (nrp) (void)hipFree(nrp);
+        return a;
+    }
+    k_fill_u32<<<grid_for(cap), 256, 0, st>>>(npool, cap, kTomb);
+    PDG_HIP(ctx, hipMemsetAsync(nrp, 0, cap * ctx->RP * 8 + 256, st));
+    PDG_HIP(ctx, hipMemsetAsync(nrz, 0, cap * ctx->ZW * 4 + 256, st));
+    k_relocate<<<grid_for(n * 64), 256, 0, st>>>(
+        n, nullptr, nullptr, ncap, noff, 0, 1, ctx->d_off, ctx->d_cnt, ctx->d_cap, ctx->d_pool,
+        npool, ctx->d_ipos, ctx->d_rec_p, nrp, ctx->RP, ctx->d_rec_z, nrz, ctx->ZW);
+    PDG_HIP(ctx, hipGetLastError());
+    PDG_HIP(ctx, hipStreamSynchronize(st));
+    if (ctx->d_pool) PDG_HIP(ctx, hipFree(ctx->d_pool));
+    if (ctx->d_rec_p) PDG_HIP(ctx, hipFree(ctx->d_rec_p));
+    if (ctx->d_rec_z) PDG_HIP(ctx, hipFree(ctx->d_rec_z));
+    ctx->d_pool = npool;
+    ctx->d_rec_p = nrp;
+    ctx->d_rec_z = nrz;
+    ctx->dev_pool_cap = cap;
+    ctx->pool_top = (int64_t)total;
+    return PDG_OK;
+}
+
+// Hub list and piece table from the segment counts, in node order.  Hubs
+// are split only with 32 or more chains and while a hub piece kernel's LDS
+// chunk holds at least the records of one step.  flag / pieces / hidx /
+// pidx: scratch of n entries.
+static pdg_status rebuild_hubs(pdg_ctx *ctx, uint32_t *flag, uint32_t *pieces, uint32_t *hidx,
+                               uint32_t *pidx, void *tmp, size_t tb)
+{
     ctx->hub_thr = 0;
     ctx->nh = ctx->np = 0;
     if (ctx->LPI < 32) return PDG_OK;
@@ -658,19 +542,16 @@ static pdg_status rebuild_hubs(pdg_ctx *ctx)
     const int64_t zb = (8 * D + 15) / 16 * 16;
     const int64_t K = (4096 - zb - 48) / (RP * 8 + 4 * zr);
     if (K < (ctx->LPI == 32 ? 2 : 1)) return PDG_OK;
-    std::vector<uint32_t> hn, hp{0}, pn_node, pf, pn;
-    for (int64_t i = 0; i < ctx->n; ++i) {
-        const uint32_t c = st.node[i].cnt;
-        if (c <= kHubThreshold) continue;
-        hn.push_back((uint32_t)i);
-        for (uint32_t f = 0; f < c; f += kHubPiece) {
-            pn_node.push_back((uint32_t)i);
-            pf.push_back(f);
-            pn.push_back(std::min(kHubPiece, c - f));
-        }
-        hp.push_back((uint32_t)pf.size());
-    }
-    const int64_t nh = (int64_t)hn.size(), np = (int64_t)pf.size();
+    const int64_t n = ctx->n;
+    const hipStream_t st = ctx->stream;
+    k_hub_count<<<grid_for(n), 256, 0, st>>>(n, ctx->d_cnt, kHubThreshold, kHubPiece, flag, pieces);
+    PDG_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp, tb, flag, hidx, (int)n, st));
+    PDG_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp, tb, pieces, pidx, (int)n, st));
+    k_scan_total<<<1, 64, 0, st>>>(n, flag, hidx, &ctx->d_sum->nh);
+    k_scan_total<<<1, 64, 0, st>>>(n, pieces, pidx, &ctx->d_sum->np);
+    EditSummary h;
+    PDG_TRY(read_sum(ctx, &h));
+    const int64_t nh = h.nh, np = h.np;
     if (nh == 0) return PDG_OK;
     const int64_t words = nh + (nh + 1) + 3 * np;
     if (words > ctx->hub_cap) {
@@ -688,28 +569,27 @@ static pdg_status rebuild_hubs(pdg_ctx *ctx)
         PDG_TRY(dalloc(ctx, (void **)&ctx->d_part, pd * 8));
         ctx->part_cap = pd;
     }
-    std::vector<uint32_t> all;
-    all.reserve(words);
-    all.insert(all.end(), hn.begin(), hn.end());
-    all.insert(all.end(), hp.begin(), hp.end());
-    all.insert(all.end(), pn_node.begin(), pn_node.end());
-    all.insert(all.end(), pf.begin(), pf.end());
-    all.insert(all.end(), pn.begin(), pn.end());
-    PDG_HIP(ctx, hipMemcpyAsync(ctx->d_hub, all.data(), words * 4, hipMemcpyHostToDevice,
-                                ctx->stream));
-    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    k_hub_fill<<<grid_for(n), 256, 0, st>>>(n, ctx->d_cnt, kHubPiece, flag, hidx, pidx,
+                                            (uint32_t)nh, (uint32_t)np, ctx->d_hub);
+    PDG_HIP(ctx, hipGetLastError());
     ctx->nh = nh;
     ctx->np = np;
     ctx->hub_thr = kHubThreshold;
     return PDG_OK;
 }
 
+struct NonZeroU64 {
+    __host__ __device__ bool operator()(const uint64_t &v) const { return v != 0; }
+};
+
 static void free_all(pdg_ctx *ctx)
 {
     void *ps[] = {ctx->d_q,     ctx->d_lam,   ctx->d_x,     ctx->d_counts, ctx->d_src,
                   ctx->d_dst,   ctx->d_uid,   ctx->d_sq,    ctx->d_params, ctx->d_ipos,
                   ctx->d_off,   ctx->d_cnt,   ctx->d_pool,  ctx->d_rec_p,  ctx->d_rec_z,
-                  ctx->d_flag,  ctx->d_scratch, ctx->d_base, ctx->d_hub, ctx->d_part};
+                  ctx->d_flag,  ctx->d_scratch, ctx->d_base, ctx->d_hub, ctx->d_part,
+                  ctx->d_free,  ctx->d_gen,   ctx->d_claim, ctx->d_cap,    ctx->d_nlive,
+                  ctx->d_mark,  ctx->d_sum};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -782,7 +662,14 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
         (s = dalloc(ctx, (void **)&ctx->d_ipos, SP * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_off, N4 * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_cnt, N4 * 4)) ||
-        (s = dalloc(ctx, (void **)&ctx->d_flag, 64)))
+        (s = dalloc(ctx, (void **)&ctx->d_flag, 64)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_free, SP * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_gen, SP * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_claim, SP * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_cap, N4 * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_nlive, N4 * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_mark, N4 * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_sum, sizeof(EditSummary))))
         return bail(s);
     if (hipMemsetAsync(ctx->d_uid, 0, SP * 8, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_src, 0, SP * 4, ctx->stream) != hipSuccess ||
@@ -794,17 +681,17 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
         hipMemsetAsync(ctx->d_counts, 0, N4 * ctx->QM * 4, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_base, 0, N4 * ctx->QM * 8, ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->d_x, 0, N * ctx->C, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        hipMemsetAsync(ctx->d_gen, 0, SP * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_cap, 0, N4 * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_nlive, 0, N4 * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_mark, 0, N4 * 4, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->d_sum, 0, sizeof(EditSummary), ctx->stream) != hipSuccess)
         return bail(fail(ctx, PDG_EHIP, "initial clear failed"));
-    Store &st = ctx->st;
-    try {
-        st.S = S;
-        st.slot.assign(S, SlotRec{0, 0, 0, 0, 0, 0, 0});
-        st.free_stack.resize(S);
-        for (int64_t j = 0; j < S; ++j) st.free_stack[j] = (int32_t)(S - 1 - j);
-    } catch (...) {
-        return bail(fail(ctx, PDG_ENOMEM, "host allocation failed"));
-    }
+    k_store_init<<<grid_for(S), 256, 0, ctx->stream>>>(S, ctx->d_free, ctx->d_claim);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return bail(fail(ctx, PDG_EHIP, "store initialisation failed"));
+    ctx->S = S;
+    ctx->ftop = S;
     *out = ctx;
     return PDG_OK;
 }
@@ -846,9 +733,6 @@ pdg_status pdg_set_nodes(pdg_ctx *ctx, int64_t n, const int32_t *d_q, const void
         PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
         ctx->uq = std::all_of(hq.begin(), hq.end(), [&](int32_t v) { return v == ctx->QM; });
     }
-    Store &st = ctx->st;
-    st.node.assign(n, NodeRec{0, 0, 0, 0});
-    st.mark.assign(n, 0);
     ctx->n = n;
     PDG_HIP(ctx, hipMemsetAsync(ctx->d_off, 0, n * 4, ctx->stream));
     PDG_HIP(ctx, hipMemsetAsync(ctx->d_cnt, 0, n * 4, ctx->stream));
@@ -869,130 +753,99 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     if (m < 0) return fail(ctx, PDG_EINVAL, "m < 0");
     if (m == 0) return PDG_OK;
     if (!d_src || !d_dst || !d_log_phi) return fail(ctx, PDG_EINVAL, "null pointer");
+    if (m > ctx->ftop) return fail(ctx, PDG_ECAPACITY, "edge capacity exhausted");
+    if (m > (1ll << 29)) return fail(ctx, PDG_EINVAL, "more than 2^29 edges in one batch");
     PDG_TRY(set_dev(ctx));
-    Store &st = ctx->st;
-    if ((int64_t)st.free_stack.size() < m) return fail(ctx, PDG_ECAPACITY, "edge capacity exhausted");
-    std::vector<int32_t> hs(m), hd(m);
-    PDG_HIP(ctx, hipMemcpyAsync(hs.data(), d_src, m * 4, hipMemcpyDeviceToHost, ctx->stream));
-    PDG_HIP(ctx, hipMemcpyAsync(hd.data(), d_dst, m * 4, hipMemcpyDeviceToHost, ctx->stream));
-    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (int64_t k = 0; k < m; ++k) {
-        if (hs[k] < 0 || hs[k] >= ctx->n || hd[k] < 0 || hd[k] >= ctx->n)
-            return fail(ctx, PDG_EINVAL, "edge endpoint out of range");
-        if (hs[k] == hd[k]) return fail(ctx, PDG_EINVAL, "self-loop is not a pairwise factor");
-    }
-    for (int64_t k = 0; k < m; ++k)
-        if (st.slot[st.free_stack[st.free_stack.size() - 1 - k]].gen == 0xFFFFFFFFu)
-            return fail(ctx, PDG_ECAPACITY, "uid space of a slot exhausted");
-    // tables must be finite before anything changes
-    PDG_TRY(clear_flag(ctx));
-    launch_check(ctx->QM, ctx->cfg.precision == PDG_PRECISION_F64, m, d_src, d_dst, ctx->d_q,
-                 d_log_phi, ctx->d_flag, ctx->stream);
-    PDG_HIP(ctx, hipGetLastError());
-    uint32_t bad = 0;
-    PDG_TRY(read_flag(ctx, &bad));
-    if (bad) return fail(ctx, PDG_ENONPOS, "non-finite log factor entry");
+    const hipStream_t st = ctx->stream;
+    const int64_t n = ctx->n, m2 = 2 * m, mn = std::max(m2, n);
+    EditSummary *sum = ctx->d_sum;
+    const size_t tb = prim_bytes(m2, n);
+    const int64_t bytes = 7 * Carve::size<uint32_t>(m2) + 2 * Carve::size<uint64_t>(mn) +
+                          3 * Carve::size<int32_t>(m) + 4 * Carve::size<uint32_t>(n) +
+                          a256((int64_t)tb);
+    void *sp;
+    PDG_TRY(scratch(ctx, bytes, &sp));
+    Carve cv{static_cast<char *>(sp)};
+    uint32_t *keys = cv.take<uint32_t>(m2), *vals = cv.take<uint32_t>(m2);
+    uint32_t *keys2 = cv.take<uint32_t>(m2), *vals2 = cv.take<uint32_t>(m2);
+    uint32_t *uniq = cv.take<uint32_t>(m2), *runlen = cv.take<uint32_t>(m2);
+    uint32_t *runoff = cv.take<uint32_t>(m2);
+    uint64_t *ncap = cv.take<uint64_t>(mn), *noff = cv.take<uint64_t>(mn);
+    int32_t *dslot = cv.take<int32_t>(m), *dqs = cv.take<int32_t>(m), *dqd = cv.take<int32_t>(m);
+    uint32_t *hflag = cv.take<uint32_t>(n), *hpieces = cv.take<uint32_t>(n);
+    uint32_t *hidx = cv.take<uint32_t>(n), *pidx = cv.take<uint32_t>(n);
+    void *tmp = cv.take<char>((int64_t)tb);
 
-    // slots and uids
-    std::vector<int32_t> slots(m);
-    std::vector<uint64_t> uids(m);
-    const int64_t fs0 = (int64_t)st.free_stack.size();
-    for (int64_t k = 0; k < m; ++k) {
-        if (k + kAhead < m) prefetch_w(&st.slot[st.free_stack[fs0 - 1 - (k + kAhead)]]);
-        const int32_t s = st.free_stack.back();
-        st.free_stack.pop_back();
-        st.slot[s].gen += 1;
-        const uint64_t u = ((uint64_t)st.slot[s].gen << 32) | (uint32_t)s;
-        slots[k] = s;
-        uids[k] = u;
-        st.slot[s].uid = u;
-        st.slot[s].src = hs[k];
-        st.slot[s].dst = hd[k];
-        st.hwm = std::max<int64_t>(st.hwm, (int64_t)s + 1);
+    // 1. everything checked before anything changes
+    PDG_TRY(reset_sum(ctx));
+    launch_check_insert(ctx, m, d_src, d_dst, d_log_phi);
+    EditSummary h;
+    PDG_TRY(read_sum(ctx, &h));
+    if (h.flags & 1u) return fail(ctx, PDG_EINVAL, "edge endpoint out of range");
+    if (h.flags & 2u) return fail(ctx, PDG_EINVAL, "self-loop is not a pairwise factor");
+    if (h.flags & 4u) return fail(ctx, PDG_ECAPACITY, "uid space of a slot exhausted");
+    if (h.flags & 8u) return fail(ctx, PDG_ENONPOS, "non-finite log factor entry");
+
+    // 2. the batch's incidence entries grouped by node, batch order inside a
+    //    node (stable sort); the capacity the full segments need
+    k_insert_entries<<<grid_for(m2), 256, 0, st>>>(m, d_src, d_dst, ctx->d_free, ctx->ftop, keys,
+                                                   vals);
+    {
+        size_t t2 = tb;
+        PDG_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, t2, keys, keys2, vals, vals2, (int)m2,
+                                                        0, key_bits(n), st));
+        t2 = tb;
+        PDG_HIP(ctx, hipcub::DeviceRunLengthEncode::Encode(tmp, t2, keys2, uniq, runlen,
+                                                           &sum->runs, (int)m2, st));
+        t2 = tb;
+        PDG_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp, t2, runlen, runoff, (int)m2, st));
     }
-    st.live += m;
-    // incidence: room first (relocation or full compaction), then appends in batch order
-    Patches P;
-    std::vector<uint32_t> &need = st.mark;  // reset for the touched nodes before returning
-    std::vector<int64_t> touched;
-    try {
-        touched.reserve(2 * m);
-        for (int64_t k = 0; k < m; ++k) {
-            if (k + kAhead < m) {
-                prefetch_w(&need[hs[k + kAhead]]);
-                prefetch_w(&need[hd[k + kAhead]]);
-            }
-            if (need[hs[k]]++ == 0) touched.push_back(hs[k]);
-            if (need[hd[k]]++ == 0) touched.push_back(hd[k]);
-        }
-    } catch (...) {
-        for (int64_t k = 0; k < m; ++k) need[hs[k]] = need[hd[k]] = 0;
-        return fail(ctx, PDG_ENOMEM, "host allocation failed");
+    k_room<<<grid_for(m2), 256, 0, st>>>(m2, &sum->runs, uniq, runlen, ctx->d_cnt, ctx->d_cap,
+                                         ctx->d_nlive, ncap);
+    {
+        size_t t2 = tb;
+        PDG_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp, t2, ncap, noff, (int)m2, st));
     }
-    struct Reset {
-        std::vector<uint32_t> &v;
-        const std::vector<int64_t> &idx;
-        ~Reset() { for (int64_t i : idx) v[i] = 0; }
-    } reset_need{need, touched};
-    uint64_t room = 0;
-    for (size_t k = 0; k < touched.size(); ++k) {
-        if (k + kAhead < touched.size()) prefetch_w(&st.node[touched[k + kAhead]]);
-        const int64_t i = touched[k];
-        if (st.node[i].cnt + need[i] > st.node[i].cap) {
-            const uint32_t want = st.node[i].nlive + need[i];
-            room += want + slack_for(want);
-        }
+    k_scan_total<<<1, 64, 0, st>>>(m2, ncap, noff, &sum->room);
+    PDG_TRY(read_sum(ctx, &h));
+    const int64_t runs = h.runs;
+
+    // 3. room: move the full segments to the end of the pool, or lay every
+    //    segment out again when the pool is too small
+    if ((uint64_t)ctx->pool_top + h.room > (uint64_t)ctx->dev_pool_cap) {
+        PDG_TRY(full_relayout(ctx, runs, uniq, runlen, ncap, noff, tmp, tb));
+    } else if (h.room) {
+        k_relocate<<<grid_for(runs * 64), 256, 0, st>>>(
+            runs, nullptr, uniq, ncap, noff, (uint64_t)ctx->pool_top, 0, ctx->d_off, ctx->d_cnt,
+            ctx->d_cap, ctx->d_pool, ctx->d_pool, ctx->d_ipos, ctx->d_rec_p, ctx->d_rec_p,
+            ctx->RP, ctx->d_rec_z, ctx->d_rec_z, ctx->ZW);
+        PDG_HIP(ctx, hipGetLastError());
+        ctx->pool_top += (int64_t)h.room;
     }
-    if ((uint64_t)st.pool_top + room > (uint64_t)st.pool.size()) {
-        PDG_TRY(full_compact(ctx, need, P));
-    } else {
-        for (int64_t i : touched)
-            if (st.node[i].cnt + need[i] > st.node[i].cap) relocate(ctx, i, need[i], P);
-    }
-    P.idx.reserve(P.idx.size() + 2 * m);
-    P.val.reserve(P.val.size() + 2 * m);
-    P.ip_key.reserve(P.ip_key.size() + 2 * m);
-    P.ip_val.reserve(P.ip_val.size() + 2 * m);
-    for (int64_t k = 0; k < m; ++k) {
-        if (k + kAhead < m) {  // node headers ahead, then the pool lines they point at
-            prefetch_w(&st.node[hs[k + kAhead]]);
-            prefetch_w(&st.node[hd[k + kAhead]]);
-        }
-        if (k + kAhead / 2 < m) {
-            const NodeRec &a = st.node[hs[k + kAhead / 2]], &b = st.node[hd[k + kAhead / 2]];
-            prefetch_w(st.pool.data() + a.off + a.cnt);
-            prefetch_w(st.pool.data() + b.off + b.cnt);
-        }
-        append(ctx, hs[k], ((uint32_t)slots[k] << 1) | 0u, P);
-        append(ctx, hd[k], ((uint32_t)slots[k] << 1) | 1u, P);
-    }
-    // device: incidence structure and records (moves, ipos), then slot
-    // arrays, decomposition of the new tables, and their records
-    PDG_TRY(upload(ctx, P, touched));
-    PDG_TRY(rebuild_hubs(ctx));
-    const int64_t nn = (int64_t)touched.size();
-    std::vector<uint32_t> hnodes(touched.begin(), touched.end());
-    void *s;
-    PDG_TRY(scratch(ctx, 8 * m + 4 * m * 3 + 4 * nn + 64, &s));
-    uint64_t *du = (uint64_t *)s;
-    int32_t *dslot = (int32_t *)(du + m), *dqs = dslot + m, *dqd = dqs + m;
-    uint32_t *dnodes = (uint32_t *)(dqd + m);
-    PDG_HIP(ctx, hipMemcpyAsync(dnodes, hnodes.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
-    PDG_HIP(ctx, hipMemcpyAsync(du, uids.data(), m * 8, hipMemcpyHostToDevice, ctx->stream));
-    PDG_HIP(ctx, hipMemcpyAsync(dslot, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
-    k_slot_write<<<grid_for(m), 256, 0, ctx->stream>>>(m, dslot, d_src, d_dst, du, ctx->d_q,
-                                                       ctx->d_src, ctx->d_dst, ctx->d_uid,
-                                                       ctx->d_sq, dqs, dqd, d_uid_out);
+
+    // 4. slots and uids, appends, decomposition, records, base
+    k_slot_write<<<grid_for(m), 256, 0, st>>>(m, ctx->d_free, ctx->ftop, d_src, d_dst, ctx->d_q,
+                                              ctx->d_gen, ctx->d_src, ctx->d_dst, ctx->d_uid,
+                                              ctx->d_sq, dslot, dqs, dqd, d_uid_out, sum);
+    k_append_first<<<grid_for(runs), 256, 0, st>>>(runs, &sum->runs, uniq, runoff, ctx->d_mark);
+    k_append_entries<<<grid_for(m2), 256, 0, st>>>(m2, keys2, vals2, ctx->d_mark, ctx->d_off,
+                                                   ctx->d_cnt, ctx->d_pool, ctx->d_ipos);
+    k_append_heads<<<grid_for(runs), 256, 0, st>>>(runs, &sum->runs, uniq, runlen, ctx->d_cnt,
+                                                   ctx->d_nlive, ctx->d_mark);
     PDG_HIP(ctx, hipGetLastError());
+    ctx->ftop -= m;
+    ctx->live += m;
     PDG_TRY(clear_flag(ctx));
     launch_decompose(ctx->QM, ctx->cfg.precision == PDG_PRECISION_F64, m, dqs, dqd, d_log_phi,
-                     dslot, ctx->d_params, ctx->d_flag, ctx->stream);
+                     dslot, ctx->d_params, ctx->d_flag, st);
+    k_write_records<<<grid_for(m * ctx->RP), 256, 0, st>>>(m, ctx->QM, dslot, ctx->d_sq,
+                                                           ctx->d_params, ctx->d_ipos,
+                                                           ctx->d_rec_p);
+    launch_node_base(ctx, runs, nullptr, uniq);
     PDG_HIP(ctx, hipGetLastError());
-    k_write_records<<<grid_for(m * ctx->RP), 256, 0, ctx->stream>>>(
-        m, ctx->QM, dslot, ctx->d_sq, ctx->d_params, ctx->d_ipos, ctx->d_rec_p);
-    launch_node_base(ctx, nn, dnodes);
-    PDG_HIP(ctx, hipGetLastError());
-    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    PDG_TRY(rebuild_hubs(ctx, hflag, hpieces, hidx, pidx, tmp, tb));
+    PDG_TRY(read_sum(ctx, &h));
+    ctx->hwm = h.hwm;
     return PDG_OK;
 }
 
@@ -1003,109 +856,62 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
     if (m < 0) return fail(ctx, PDG_EINVAL, "m < 0");
     if (m == 0) return PDG_OK;
     if (!d_uid) return fail(ctx, PDG_EINVAL, "null pointer");
+    if (m > (1ll << 30)) return fail(ctx, PDG_EINVAL, "more than 2^30 edges in one batch");
     PDG_TRY(set_dev(ctx));
-    Store &st = ctx->st;
-    std::vector<uint64_t> hu(m);
-    PDG_HIP(ctx, hipMemcpyAsync(hu.data(), d_uid, m * 8, hipMemcpyDeviceToHost, ctx->stream));
-    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    std::vector<int32_t> slots(m);
-    for (int64_t k = 0; k < m; ++k) {
-        if (k + kAhead < m) {
-            const int64_t sa = (int64_t)(hu[k + kAhead] & 0xFFFFFFFFull);
-            if (sa < st.S) prefetch_w(&st.slot[sa]);
-        }
-        const uint64_t u = hu[k];
-        const int64_t s = (int64_t)(u & 0xFFFFFFFFull);
-        if (u == 0 || s >= st.S || st.slot[s].uid != u) {
-            for (int64_t j = 0; j < k; ++j) st.slot[slots[j]].uid = hu[j];
-            return fail(ctx, PDG_ENOTFOUND, "uid " + std::to_string(u) + " is not a live edge");
-        }
-        slots[k] = (int32_t)s;
-        st.slot[s].uid = 0;  // also catches a uid repeated within the batch
-    }
-    Patches P;
-    std::vector<int64_t> touched;
-    std::vector<uint32_t> recs, hnodes;
-    recs.reserve(2 * m);
-    hnodes.reserve(2 * m);
-    P.idx.reserve(2 * m);
-    P.val.reserve(2 * m);
-    st.free_stack.reserve(st.free_stack.size() + m);
-    for (int64_t k = 0; k < m; ++k) {
-        if (k + kAhead < m) {  // the slot lines were fetched by the validation loop
-            const SlotRec &r = st.slot[slots[k + kAhead]];
-            prefetch_w(&st.node[r.src]);
-            prefetch_w(&st.node[r.dst]);
-        }
-        if (k + kAhead / 2 < m) {
-            const SlotRec &r = st.slot[slots[k + kAhead / 2]];
-            prefetch_w(st.pool.data() + st.node[r.src].off + r.pos0);
-            prefetch_w(st.pool.data() + st.node[r.dst].off + r.pos1);
-        }
-        const int32_t s = slots[k];
-        const int32_t a = st.slot[s].src, b = st.slot[s].dst;
-        const uint32_t ia = st.node[a].off + st.slot[s].pos0, ib = st.node[b].off + st.slot[s].pos1;
-        st.pool[ia] = kTomb;
-        st.pool[ib] = kTomb;
-        P.idx.push_back(ia);
-        P.val.push_back(kTomb);
-        P.idx.push_back(ib);
-        P.val.push_back(kTomb);
-        recs.push_back(ia);
-        recs.push_back(ib);
-        hnodes.push_back((uint32_t)a);
-        hnodes.push_back((uint32_t)b);
-        st.node[a].nlive--;
-        st.node[b].nlive--;
-        st.free_stack.push_back(s);
-    }
-    st.live -= m;
-    PDG_TRY(upload(ctx, P, touched));
-    {  // distinct endpoints, first-seen order
-        size_t w = 0;
-        for (size_t k = 0; k < hnodes.size(); ++k)
-            if (st.mark[hnodes[k]]++ == 0) hnodes[w++] = hnodes[k];
-        hnodes.resize(w);
-        for (uint32_t i : hnodes) st.mark[i] = 0;
-    }
-    const int64_t nn = (int64_t)hnodes.size();
+    const hipStream_t st = ctx->stream;
+    EditSummary *sum = ctx->d_sum;
     void *sp;
-    PDG_TRY(scratch(ctx, 4 * m + 8 * m + 4 * nn + 768, &sp));
-    int32_t *dsl = (int32_t *)sp;
-    uint32_t *drec = (uint32_t *)((char *)sp + ((4 * m + 255) / 256) * 256);
-    uint32_t *dnodes = (uint32_t *)((char *)drec + ((8 * m + 255) / 256) * 256);
-    PDG_HIP(ctx, hipMemcpyAsync(dsl, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
-    PDG_HIP(ctx, hipMemcpyAsync(drec, recs.data(), 2 * m * 4, hipMemcpyHostToDevice, ctx->stream));
-    PDG_HIP(ctx, hipMemcpyAsync(dnodes, hnodes.data(), nn * 4, hipMemcpyHostToDevice, ctx->stream));
-    k_slot_clear<<<grid_for(m), 256, 0, ctx->stream>>>(m, dsl, ctx->d_uid);
-    k_clear_records<<<grid_for(2 * m * ctx->RP), 256, 0, ctx->stream>>>(2 * m, ctx->RP, drec,
-                                                                       ctx->d_rec_p);
-    launch_node_base(ctx, nn, dnodes);
+    PDG_TRY(scratch(ctx, Carve::size<uint32_t>(2 * m), &sp));
+    uint32_t *list = static_cast<uint32_t *>(sp);
+
+    // every uid live and named once, else nothing changes
+    PDG_TRY(reset_sum(ctx));
+    k_check_remove<<<grid_for(m), 256, 0, st>>>(m, d_uid, ctx->S, ctx->d_uid, ctx->d_claim, sum);
+    k_check_remove2<<<grid_for(m), 256, 0, st>>>(m, d_uid, ctx->S, ctx->d_uid, ctx->d_claim, sum);
+    k_claim_reset<<<grid_for(m), 256, 0, st>>>(m, d_uid, ctx->S, ctx->d_uid, ctx->d_claim);
+    EditSummary h;
+    PDG_TRY(read_sum(ctx, &h));
+    if (h.bad != 0xFFFFFFFFu) {
+        uint64_t u = 0;
+        PDG_HIP(ctx, hipMemcpyAsync(&u, d_uid + h.bad, 8, hipMemcpyDeviceToHost, st));
+        PDG_HIP(ctx, hipStreamSynchronize(st));
+        return fail(ctx, PDG_ENOTFOUND,
+                    "uid " + std::to_string(u) + " is not a live edge or is repeated in the batch");
+    }
+    k_clear_edge_records<<<grid_for(2 * m * ctx->RP), 256, 0, st>>>(m, ctx->RP, d_uid, ctx->d_ipos,
+                                                                    ctx->d_rec_p);
+    k_remove_apply<<<grid_for(m), 256, 0, st>>>(m, d_uid, ctx->d_src, ctx->d_dst, ctx->d_ipos,
+                                                ctx->d_pool, ctx->d_nlive, ctx->d_uid,
+                                                ctx->d_free, ctx->ftop, ctx->d_mark, list, sum);
+    launch_node_base(ctx, 2 * m, &sum->nlist, list);
+    k_unmark<<<grid_for(2 * m), 256, 0, st>>>(2 * m, &sum->nlist, list, ctx->d_mark);
     PDG_HIP(ctx, hipGetLastError());
-    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->ftop += m;
+    ctx->live -= m;
+    PDG_HIP(ctx, hipStreamSynchronize(st));
     return PDG_OK;
 }
 
 pdg_status pdg_num_edges(pdg_ctx *ctx, int64_t *h_live)
 {
     if (!ctx || !h_live) return fail(ctx, PDG_EINVAL, "null argument");
-    *h_live = ctx->st.live;
+    *h_live = ctx->live;
     return PDG_OK;
 }
 
 pdg_status pdg_live_uids(pdg_ctx *ctx, uint64_t *d_uid_out)
 {
     if (!ctx || !d_uid_out) return fail(ctx, PDG_EINVAL, "null argument");
+    if (ctx->live == 0) return PDG_OK;
     PDG_TRY(set_dev(ctx));
-    std::vector<uint64_t> out;
-    out.reserve(ctx->st.live);
-    for (int64_t s = 0; s < ctx->st.hwm; ++s)
-        if (ctx->st.slot[s].uid) out.push_back(ctx->st.slot[s].uid);
-    if (!out.empty()) {
-        PDG_HIP(ctx, hipMemcpyAsync(d_uid_out, out.data(), out.size() * 8, hipMemcpyHostToDevice,
-                                    ctx->stream));
-        PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    }
+    size_t tb = 0;
+    PDG_HIP(ctx, hipcub::DeviceSelect::If(nullptr, tb, ctx->d_uid, d_uid_out, &ctx->d_sum->sel,
+                                          (int)ctx->hwm, NonZeroU64(), ctx->stream));
+    void *sp;
+    PDG_TRY(scratch(ctx, (int64_t)tb + 256, &sp));
+    PDG_HIP(ctx, hipcub::DeviceSelect::If(sp, tb, ctx->d_uid, d_uid_out, &ctx->d_sum->sel,
+                                          (int)ctx->hwm, NonZeroU64(), ctx->stream));
+    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PDG_OK;
 }
 
@@ -1203,7 +1009,7 @@ pdg_status pdg_dual_phase(pdg_ctx *ctx)
     if (ctx->t + 1 >= 0xFFFFFFFFll) return fail(ctx, PDG_ECAPACITY, "sweep counter exhausted");
     PDG_TRY(set_dev(ctx));
     ctx->t += 1;
-    if (ctx->st.hwm > 0) {
+    if (ctx->hwm > 0) {
         launch_dual(ctx, (uint32_t)ctx->t);
         PDG_HIP(ctx, hipGetLastError());
     }
@@ -1244,21 +1050,17 @@ pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_
     if (m == 0) return PDG_OK;
     if (!d_uid || !d_theta_out) return fail(ctx, PDG_EINVAL, "null pointer");
     PDG_TRY(set_dev(ctx));
-    std::vector<uint64_t> hu(m);
-    PDG_HIP(ctx, hipMemcpyAsync(hu.data(), d_uid, m * 8, hipMemcpyDeviceToHost, ctx->stream));
-    PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    std::vector<int32_t> slots(m);
-    for (int64_t k = 0; k < m; ++k) {
-        const int64_t s = (int64_t)(hu[k] & 0xFFFFFFFFull);
-        if (hu[k] == 0 || s >= ctx->st.S || ctx->st.slot[s].uid != hu[k])
-            return fail(ctx, PDG_ENOTFOUND, "uid is not a live edge");
-        slots[k] = (int32_t)s;
-    }
     void *sp;
     PDG_TRY(scratch(ctx, 4 * m + 64, &sp));
-    PDG_HIP(ctx, hipMemcpyAsync(sp, slots.data(), m * 4, hipMemcpyHostToDevice, ctx->stream));
-    k_get_duals<<<grid_for(m * ctx->C), 256, 0, ctx->stream>>>(m, ctx->QM, make_graph(ctx),
-                                                               (const int32_t *)sp, d_theta_out);
+    int32_t *slots = static_cast<int32_t *>(sp);
+    PDG_TRY(reset_sum(ctx));
+    k_uid_slots<<<grid_for(m), 256, 0, ctx->stream>>>(m, d_uid, ctx->S, ctx->d_uid, slots,
+                                                      ctx->d_sum);
+    EditSummary h;
+    PDG_TRY(read_sum(ctx, &h));
+    if (h.bad != 0xFFFFFFFFu) return fail(ctx, PDG_ENOTFOUND, "uid is not a live edge");
+    k_get_duals<<<grid_for(m * ctx->C), 256, 0, ctx->stream>>>(m, ctx->QM, make_graph(ctx), slots,
+                                                               d_theta_out);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PDG_OK;

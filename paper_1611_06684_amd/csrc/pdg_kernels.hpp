@@ -1234,54 +1234,6 @@ __global__ void k_set_nodes(int64_t n, int32_t QM, const int32_t *__restrict__ q
     }
 }
 
-// New edges: slot arrays.
-__global__ void k_slot_write(int64_t m, const int32_t *__restrict__ slots,
-                             const int32_t *__restrict__ src_in, const int32_t *__restrict__ dst_in,
-                             const uint64_t *__restrict__ uids, const uint8_t *__restrict__ q,
-                             int32_t *__restrict__ src, int32_t *__restrict__ dst,
-                             uint64_t *__restrict__ uid, uint8_t *__restrict__ sq,
-                             int32_t *__restrict__ qs_out, int32_t *__restrict__ qd_out,
-                             uint64_t *__restrict__ uid_out)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    const int32_t s = slots[k], a = src_in[k], b = dst_in[k];
-    src[s] = a;
-    dst[s] = b;
-    uid[s] = uids[k];
-    const uint8_t qa = q[a], qb = q[b];
-    sq[s] = (uint8_t)(qa | (qb << 4));
-    qs_out[k] = qa;
-    qd_out[k] = qb;
-    if (uid_out) uid_out[k] = uids[k];
-}
-
-__global__ void k_slot_clear(int64_t m, const int32_t *__restrict__ slots, uint64_t *__restrict__ uid)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) uid[slots[k]] = 0;
-}
-
-// pool[idx[k]] = val[k]
-__global__ void k_scatter_u32(int64_t m, const uint32_t *__restrict__ idx,
-                              const uint32_t *__restrict__ val, uint32_t *__restrict__ pool)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) pool[idx[k]] = val[k];
-}
-
-// off[node[k]] = o[k], cnt[node[k]] = c[k]
-__global__ void k_scatter_nodes(int64_t m, const uint32_t *__restrict__ node,
-                                const uint32_t *__restrict__ o, const uint32_t *__restrict__ c,
-                                uint32_t *__restrict__ off, uint32_t *__restrict__ cnt)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) {
-        off[node[k]] = o[k];
-        cnt[node[k]] = c[k];
-    }
-}
-
 // theta of m edges (given by slot) for every chain: out [m][C], bit d for the
 // edge's own entries d = (a-1)(q_dst-1) + (b-1), read from its src record.
 __global__ void k_get_duals(int64_t m, int32_t QM, Graph g, const int32_t *__restrict__ slots,
@@ -1329,22 +1281,14 @@ __global__ void k_write_records(int64_t m, int32_t QM, const int32_t *__restrict
     rec_p[(uint64_t)ipos[2 * s + 1] * RP + j] = vd;
 }
 
-// Removed edges: zero their records (a zero record adds nothing to any field).
-__global__ void k_clear_records(int64_t m, int32_t RP, const uint32_t *__restrict__ rec,
-                                double *__restrict__ rec_p)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= m * RP) return;
-    const int64_t k = idx / RP;
-    rec_p[(uint64_t)rec[k] * RP + (idx - k * RP)] = 0.0;
-}
-
-// base of the listed nodes: lam plus the c0 of each live incidence (from the
-// edge's parameter block, the node's side).  One wave per node: lane l sums
+// base of the listed nodes (the first *count of them when count is given):
+// lam plus the c0 of each live incidence (from the edge's parameter block,
+// the node's side).  One wave per node: lane l sums
 // records l, l + 64, ... and the wave adds the lanes' sums in a fixed butterfly,
 // so the result depends only on the node's record list.
 template <int QM>
-__global__ __launch_bounds__(256) void k_node_base(int64_t nn, const uint32_t *__restrict__ nodes,
+__global__ __launch_bounds__(256) void k_node_base(int64_t nn, const uint32_t *__restrict__ count,
+                                                   const uint32_t *__restrict__ nodes,
                                                    const double *__restrict__ lam,
                                                    const uint32_t *__restrict__ off,
                                                    const uint32_t *__restrict__ cnt,
@@ -1354,7 +1298,7 @@ __global__ __launch_bounds__(256) void k_node_base(int64_t nn, const uint32_t *_
 {
     const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (k >= nn) return;
+    if (k >= nn || (count && k >= (int64_t)*count)) return;
     const uint64_t i = nodes[k];
     double acc[QM];
 #pragma unroll
@@ -1377,45 +1321,6 @@ __global__ __launch_bounds__(256) void k_node_base(int64_t nn, const uint32_t *_
     for (int a = 1; a < QM; ++a)
         if (lane == a) v = acc[a];
     if (lane < QM) base[i * QM + lane] = lam[i * QM + lane] + v;
-}
-
-// Moved incidence entries: record from[k] -> to[k] (u64 and u32 granules).
-__global__ void k_move_rec_p(int64_t m, int32_t RP, const uint32_t *__restrict__ from,
-                             const uint32_t *__restrict__ to, const double *__restrict__ src,
-                             double *__restrict__ dst)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= m * RP) return;
-    const int64_t k = idx / RP;
-    const int j = (int)(idx - k * RP);
-    dst[(uint64_t)to[k] * RP + j] = src[(uint64_t)from[k] * RP + j];
-}
-
-__global__ void k_move_rec_z(int64_t m, int64_t ZW, const uint32_t *__restrict__ from,
-                             const uint32_t *__restrict__ to, const uint32_t *__restrict__ src,
-                             uint32_t *__restrict__ dst)
-{
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= m * ZW) return;
-    const int64_t k = idx / ZW;
-    const int64_t j = idx - k * ZW;
-    dst[(uint64_t)to[k] * ZW + j] = src[(uint64_t)from[k] * ZW + j];
-}
-
-// ipos[key[k]] = val[k], key = 2 slot + side
-__global__ void k_set_ipos(int64_t m, const uint32_t *__restrict__ key,
-                           const uint32_t *__restrict__ val, uint32_t *__restrict__ ipos)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) ipos[key[k]] = val[k];
-}
-
-// live uids in slot order: out[k] for the k-th live slot (prefix given by host)
-__global__ void k_gather_u64(int64_t m, const int32_t *__restrict__ slots,
-                             const uint64_t *__restrict__ v, uint64_t *__restrict__ out)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) out[k] = v[slots[k]];
 }
 
 __global__ void k_marginals(int64_t nq, const uint32_t *__restrict__ counts, double inv,

@@ -306,6 +306,90 @@ def test_edits_then_teacher_forced():
     s.close()
 
 
+def _new_edges(rng, model, k, focus=None, share=1.0):
+    """k random edges (a share of them with src in `focus`), tables N(0, 0.5)
+    zeroed beyond each endpoint's q."""
+    n, qm = model.n, model.q_max
+    src = rng.integers(0, n, size=k)
+    if focus is not None:
+        pick = rng.random(k) < share
+        src[pick] = rng.choice(np.asarray(focus), size=int(pick.sum()))
+    dst = (src + 1 + rng.integers(0, n - 1, size=k)) % n
+    Lam = rng.normal(0.0, 0.5, size=(k, qm, qm))
+    for e in range(k):
+        Lam[e, model.q[src[e]]:, :] = 0.0
+        Lam[e, :, model.q[dst[e]]:] = 0.0
+    return src.astype(np.int32), dst.astype(np.int32), Lam.astype(model.Lam.dtype)
+
+
+def test_store_growth_relocation_and_relayout():
+    """Edit batches that grow one node into a hub, empty it and refill it,
+    remove 40 % of the edges, and add more edges than the pool holds: segment
+    relocation, full re-layout (fresh buffers), tombstone compaction and the
+    hub table all run on the device.  After every batch the live uid set is
+    checked and a teacher-forced sweep matches the oracle; a second context
+    replaying the same batches issues the same uids and, after free sweeps,
+    holds the same state bit for bit (the store's decisions are deterministic)."""
+    import torch
+    model = W.random_graph(600, 800, [2, 3, 4], seed=31, dtype="f32")
+    C, seed = 64, 9
+    cap = 3400
+    a = _sampler(model, C, seed, edge_capacity=cap)
+    b = _sampler(model, C, seed, edge_capacity=cap)
+    rng = np.random.default_rng(32)
+    live_uid = _u64(a.uids).copy()
+    assert np.array_equal(live_uid, _u64(b.uids))
+    live = dict(src=model.src.copy(), dst=model.dst.copy(), Lam=model.Lam.copy())
+    a.init()
+    b.init()
+
+    def insert(src, dst, Lam):
+        nonlocal live_uid
+        ua = _u64(a.insert_edges(src, dst, Lam))
+        ub = _u64(b.insert_edges(src, dst, Lam))
+        assert np.array_equal(ua, ub)
+        live_uid = np.concatenate([live_uid, ua])
+        for k, v in (("src", src), ("dst", dst), ("Lam", Lam)):
+            live[k] = np.concatenate([live[k], v])
+
+    def remove(mask):
+        nonlocal live_uid
+        rem = live_uid[mask]
+        for s in (a, b):
+            s.remove_edges(torch.as_tensor(rem.view(np.int64), device=s.dev))
+        live_uid = live_uid[~mask]
+        for k in live:
+            live[k] = live[k][~mask]
+
+    steps = [
+        ("hub growth", lambda: insert(*_new_edges(rng, model, 600, focus=[0, 0, 0, 1, 2]))),
+        ("remove 40%", lambda: remove(rng.random(len(live_uid)) < 0.4)),
+        ("bulk insert", lambda: insert(*_new_edges(rng, model, 1500))),
+        ("empty the hub", lambda: remove((live["src"] == 0) | (live["dst"] == 0))),
+        ("refill the hub", lambda: insert(*_new_edges(rng, model, 300, focus=[0]))),
+    ]
+    for rnd, (name, step) in enumerate(steps):
+        step()
+        assert sorted(_u64(a.live_uids()).tolist()) == sorted(live_uid.tolist())
+        cur = W.Model(model.q, model.lam, live["src"], live["dst"], live["Lam"])
+        deg0 = int(np.count_nonzero(cur.src == 0) + np.count_nonzero(cur.dst == 0))
+        a.uids = torch.as_tensor(live_uid.view(np.int64), device=a.dev)
+        dec = oracle.decompose(cur)
+        x_in = _random_state(cur, C, 70 + rnd)
+        r = teacher_forced(a, cur, dec, seed, x_in, 20 + rnd)
+        _say(f"  {name}: live={len(live_uid)} deg(0)={deg0} {r}")
+        assert r["bad_dual"] == 0 and r["bad_x"] == 0, r
+        assert r["flagged"] <= FLAG_BUDGET * r["draws"] + 2, r
+    x0 = _random_state(model, C, 99)
+    for s in (a, b):
+        s.set_state(torch.as_tensor(x0, device=s.dev))
+        s.t = 40
+        s.sweep(3)
+    assert np.array_equal(a.state().cpu().numpy(), b.state().cpu().numpy())
+    a.close()
+    b.close()
+
+
 def test_checkpoint_resume_is_bit_exact():
     """A chain saved after t1 sweeps (state and sweep counter) and resumed in a
     fresh context continues exactly as the uninterrupted run: the generator is
