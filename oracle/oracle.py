@@ -96,6 +96,9 @@ def _declare(L):
     L.orc_num_threads.restype = ctypes.c_int
     L.orc_all_logits.argtypes = [_I64, _I64, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_all_logits.restype = ctypes.c_int
+    L.orc_log_v.argtypes = [_I64, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                            _P]
+    L.orc_log_v.restype = ctypes.c_int
 
 
 def _c(a, dtype):
@@ -251,6 +254,23 @@ def all_logits(model, dec, theta_one_chain) -> np.ndarray:
     if rc != 0:
         raise MemoryError("oracle logits failed")
     return L
+
+
+def log_v(model, dec, theta, x) -> np.ndarray:
+    """log V(x, theta) per chain (Sec. 5.2 estimator of the partition function):
+    theta [m][C] u64 (bit d), x [n][C] u8 -> [C] float64."""
+    theta = np.ascontiguousarray(theta, np.uint64).reshape(model.m, -1)
+    x = np.ascontiguousarray(x, np.uint8).reshape(model.n, -1)
+    C = x.shape[1]
+    out = np.zeros(C)
+    args, keep = _graph_args(model, dec, np.zeros(model.m, np.uint64))
+    Lam, pL = _c(model.Lam, np.float64)
+    a = [args[0], args[1], args[2], args[3], pL, args[5], args[6], args[7]]
+    rc = lib().orc_log_v(model.n, model.m, C, model.q_max, *a, theta.ctypes.data_as(_P),
+                         x.ctypes.data_as(_P), out.ctypes.data_as(_P))
+    if rc != 0:
+        raise MemoryError("oracle log V failed")
+    return out
 
 
 # --------------------------------------------------- single elements (sampled checks)

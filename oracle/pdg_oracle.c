@@ -35,6 +35,9 @@
  *   orc_primal_node     nodes; each node is a categorical draw by inverse CDF.
  *   orc_run             alternating blockwise Gibbs (Sec. 5.1): dual phase then
  *                       primal phase per sweep, marginal counting after burn-in.
+ *   orc_log_v           Sec. 5.2: log of the estimator V(x, theta) =
+ *                       p~(x) p~(theta) / p~(x, theta) of the partition function,
+ *                       written with the Lemma of Sec. 3 as p~(x) / p(x | theta).
  *
  * Notation.  x_i in {0..q_i-1} node states; theta_{e,ab} in {0,1} the dual of
  * entry (a,b), a,b >= 1, of edge e; y = [x_src == a], y' = [x_dst == b] the
@@ -599,6 +602,52 @@ int orc_all_logits(int64_t n, int64_t m, int32_t q_max, const int32_t *q,
                           L + i * q_max);
     }
     orc_scratch_free(&w);
+    orc_graph_free(&g);
+    return err ? -1 : 0;
+}
+
+/* Sec. 5.2: V(x, theta) = p~(x) p~(theta) / p~(x, theta) has mean Z under
+ * the joint, and log V has mean log Z - I(x; theta).  The Lemma of Sec. 3
+ * gives p~(theta) / p~(x, theta) = 1 / p(x | theta), and p(x | theta)
+ * factorizes over the nodes (Sec. 4 Corollary), so per chain c
+ *   log V = sum_i lam_i(x_i) + sum_e Lam_e(x_src, x_dst)
+ *           - sum_i [L_i(x_i) - log sum_{a < q_i} exp L_i(a)]
+ * with L_i the node logits given theta (orc_node_logits_p).  Layouts: Lam
+ * [m][q_max][q_max] (the log factor tables themselves), theta [m][C], x [n][C],
+ * out [C]. */
+int orc_log_v(int64_t n, int64_t m, int32_t C, int32_t q_max, const int32_t *q,
+              const double *lam, const int32_t *src, const int32_t *dst, const double *Lam,
+              const double *par, const double *rrow, const double *rcol,
+              const uint64_t *theta, const uint8_t *x, double *out)
+{
+    orc_graph g = {n, m, C, q_max, q, lam, src, dst, 0, par, rrow, rcol, 0, 0, 0, 0};
+    if (orc_graph_build(&g)) { orc_graph_free(&g); return -1; }
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int32_t c = 0; c < C; ++c) {
+        orc_scratch w = {0, 0, 0, 0, 0, 0};
+        double log_p = 0.0, log_cond = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            log_p += lam[i * q_max + x[i * C + c]];
+        for (int64_t e = 0; e < m; ++e) {
+            const int a = x[(int64_t)src[e] * C + c], b = x[(int64_t)dst[e] * C + c];
+            log_p += Lam[(e * q_max + a) * q_max + b];
+        }
+        for (int64_t i = 0; i < n && !err; ++i) {
+            int64_t deg = g.off[i + 1] - g.off[i];
+            if (orc_scratch_fit(&w, deg)) { err = 1; break; }
+            orc_gather(&g, i, theta, c, C, &w);
+            double L[64];
+            orc_node_logits_p(q[i], lam + i * q_max, deg, w.sd, w.qo, w.pp, w.rr, w.tt, L);
+            double mx = L[0];
+            for (int a = 1; a < q[i]; ++a) if (L[a] > mx) mx = L[a];
+            double z = 0.0;
+            for (int a = 0; a < q[i]; ++a) z += exp(L[a] - mx);
+            log_cond += L[x[i * C + c]] - (mx + log(z));
+        }
+        out[c] = log_p - log_cond;
+        orc_scratch_free(&w);
+    }
     orc_graph_free(&g);
     return err ? -1 : 0;
 }

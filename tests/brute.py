@@ -7,6 +7,9 @@
   T(x -> x') = sum_theta p(theta | x) p(x' | theta), enumerating every dual
   configuration and taking the two conditionals from the oracle's probability
   functions (not from its sampler).
+* ``joint``: the primal-dual joint p(x, theta) = p(x) p(theta | x) over every
+  state and dual configuration (the x-marginal is the MRF by construction;
+  p(theta | x) from the oracle's dual probability function).
 * ``batch_means``: Monte-Carlo standard errors of marginal estimates.
 """
 from __future__ import annotations
@@ -57,20 +60,22 @@ def _softmax_rows(L, q):
     return out
 
 
-def exact_transition(model, dec):
-    """Returns (X, T) with T[s, s'] = P(x_{t} = X[s'] | x_{t-1} = X[s])."""
-    X = all_states(model.q)
-    S = X.shape[0]
+def _dual_bits(model):
     bits = []  # (edge, d, a, b)
     for e in range(model.m):
         qi, qj = int(model.q[model.src[e]]), int(model.q[model.dst[e]])
         for a in range(1, qi):
             for b in range(1, qj):
                 bits.append((e, (a - 1) * (qj - 1) + (b - 1), a, b))
-    nb = len(bits)
-    assert nb <= 14, "too many duals to enumerate"
+    assert len(bits) <= 14, "too many duals to enumerate"
+    return bits
+
+
+def _dual_probabilities(model, dec, X, bits):
+    """p(theta | x) [S][K] for every dual configuration k (bit k of the
+    enumeration = bits[k]), and the configurations as theta arrays [K][m]."""
+    S, nb = X.shape[0], len(bits)
     K = 1 << nb
-    # p(theta | x): product of independent logistic draws
     p1 = np.zeros((S, nb))
     for k, (e, d, a, b) in enumerate(bits):
         ys = (X[:, model.src[e]] == a).astype(int)
@@ -79,17 +84,36 @@ def exact_transition(model, dec):
         p1[:, k] = [tab[(int(u), int(v))] for u, v in zip(ys, yd)]
     cfg = ((np.arange(K)[:, None] >> np.arange(nb)[None, :]) & 1).astype(np.float64)
     P_th = np.exp(np.log(p1) @ cfg.T + np.log1p(-p1) @ (1.0 - cfg).T)  # [S][K]
+    TH = np.zeros((K, model.m), np.uint64)
+    for kk in range(K):
+        for k, (e, d, a, b) in enumerate(bits):
+            if (kk >> k) & 1:
+                TH[kk, e] |= np.uint64(1) << np.uint64(d)
+    return P_th, TH
+
+
+def exact_transition(model, dec):
+    """Returns (X, T) with T[s, s'] = P(x_{t} = X[s'] | x_{t-1} = X[s])."""
+    X = all_states(model.q)
+    S = X.shape[0]
+    bits = _dual_bits(model)
+    P_th, TH = _dual_probabilities(model, dec, X, bits)
+    K = P_th.shape[1]
     # p(x' | theta): product over nodes of the categorical conditionals
     P_x = np.zeros((K, S))
     for kk in range(K):
-        theta = np.zeros(model.m, np.uint64)
-        for k, (e, d, a, b) in enumerate(bits):
-            if (kk >> k) & 1:
-                theta[e] |= np.uint64(1) << np.uint64(d)
-        L = oracle.all_logits(model, dec, theta)
+        L = oracle.all_logits(model, dec, TH[kk])
         pr = _softmax_rows(L, model.q)
         P_x[kk] = np.prod(pr[np.arange(model.n)[None, :], X], axis=1)
     return X, P_th @ P_x
+
+
+def joint(model, dec):
+    """Returns (X [S][n], TH [K][m] u64, P [S][K]) with P[s, k] = p(X[s], TH[k])."""
+    X, px = stationary(model)
+    bits = _dual_bits(model)
+    P_th, TH = _dual_probabilities(model, dec, X, bits)
+    return X, TH, px[:, None] * P_th
 
 
 def batch_means(series_counts: np.ndarray) -> tuple[np.ndarray, np.ndarray]:

@@ -45,6 +45,11 @@ MUTANTS = {
                            "if (u < F[a]) { x = a; break; }"),
     "cdf_not_cumulative": ("F[a] = acc;", "F[a] = exp(L[a] - mx);"),
     "primal_node_quad_word": ("(int)(node % 4));", "(int)(c % 4));"),
+    "logv_sign": ("out[c] = log_p - log_cond;", "out[c] = log_p + log_cond;"),
+    "logv_no_shift": ("log_cond += L[x[i * C + c]] - (mx + log(z));",
+                      "log_cond += L[x[i * C + c]] - log(z);"),
+    "logv_edge_transposed": ("log_p += Lam[(e * q_max + a) * q_max + b];",
+                             "log_p += Lam[(e * q_max + b) * q_max + a];"),
     "init_floor": ("x[i * C + c] = (uint8_t)floor(u * q[i]);",
                    "x[i * C + c] = (uint8_t)floor(u * (q[i] - 1));"),
 }
@@ -63,6 +68,8 @@ FAST_PINS = [
     lambda: [pins.test_dual_draw_frequencies_match_conditional(a, b) for a, b in ((3, 4), (4, 2))],
     pins.test_equal_weights_draw_is_floor_uq,
     pins.test_init_is_floor_uq,
+    lambda: [pins.test_log_v_estimator_identities_by_enumeration(n, m)
+             for n, m in pins._tiny_models()],
 ]
 
 

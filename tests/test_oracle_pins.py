@@ -233,6 +233,39 @@ def test_exact_transition_detailed_balance_and_stationarity(name, model):
     assert (T > 0).all()  # strictly positive factors: one sweep reaches every state
 
 
+
+@pytest.mark.parametrize("name,model", list(_tiny_models()))
+def test_log_v_estimator_identities_by_enumeration(name, model):
+    """Sec. 5.2: under the joint p(x, theta) = p(x) p(theta | x) (every state
+    and dual configuration enumerated), V = p~(x) p~(theta) / p~(x, theta) has
+    mean Z, and log V has mean log Z - I(x; theta), where Z is the plain sum of
+    the MRF's unnormalised density and I the mutual information of the
+    enumerated joint.  Both hold only if the oracle's node logits are the exact
+    conditional p(x | theta) of the joint its dual conditional defines."""
+    dec = oracle.decompose(model)
+    X, TH, P = brute.joint(model, dec)
+    S, K = P.shape
+    np.testing.assert_allclose(P.sum(), 1.0, atol=1e-13)
+    xs = np.ascontiguousarray(X.T.astype(np.uint8))  # every state is one chain
+    logV = np.zeros((S, K))
+    for k in range(K):
+        logV[:, k] = oracle.log_v(model, dec, np.repeat(TH[k][:, None], S, axis=1), xs)
+    lp = brute.log_joint(model, X)
+    log_Z = lp.max() + np.log(np.exp(lp - lp.max()).sum())
+    # E[V] = Z (the tolerance covers the rounding of the enumerated dual
+    # probabilities near 0 and 1 under strong coupling)
+    EV = (P * np.exp(logV - log_Z)).sum()
+    np.testing.assert_allclose(EV, 1.0, rtol=1e-10)
+    # E[log V] = log Z - I(x; theta)
+    px, pth = P.sum(axis=1), P.sum(axis=0)
+    I = (P * (np.log(P) - np.log(px)[:, None] - np.log(pth)[None, :])).sum()
+    assert I > 0
+    np.testing.assert_allclose((P * logV).sum(), log_Z - I, rtol=0, atol=1e-10)
+    # V is a ratio of densities: log V = log p~(x) - log p(x | theta), so with
+    # theta fixed, log V - log p~(x) is minus the log of a distribution over x
+    for k in range(K):
+        np.testing.assert_allclose(np.exp(lp - logV[:, k]).sum(), 1.0, rtol=1e-12)
+
 def _pair(qi, qj, seed, std):
     rng = np.random.default_rng(seed)
     qm = max(qi, qj)
