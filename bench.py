@@ -1,7 +1,7 @@
 """Benchmark of the primal-dual Gibbs sweep on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--workload plain-grid|dynamic-sparse]
+                    [--workload plain-grid|dynamic-sparse|tiny]
 
 Workloads (seeded, synthetic; recipes in workloads.py):
   plain-grid (default, the headline line): 1024 x 1024 open 4-neighbour grid,
@@ -11,6 +11,9 @@ Workloads (seeded, synthetic; recipes in workloads.py):
     degree 8, q = 8, log-tables N(0, 0.15), 32 chains; every 10 sweeps 1 % of the
     live edges are removed and as many inserted (edit batches prepared on the
     device before timing; the edits themselves are timed).
+  tiny: 4 x 4 binary grid (Ising tables exp(J s s'), J ~ U(-0.3, 0.3), unaries
+    exp(h s), h ~ N(0, 0.5)), FP64, one chain: bound by latency, so its line is
+    sweeps/s (steps = sweeps, run in batches of one launch each).
 A step is one full sweep: the dual phase over every edge and chain, then the
 primal phase over every node and chain (with marginal counting).  The metric is
 chain * (|V| + |E|) updates/s with every input resident in HBM.
@@ -54,7 +57,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
-    p.add_argument("--workload", choices=["plain-grid", "dynamic-sparse"], default="plain-grid")
+    p.add_argument("--workload", choices=["plain-grid", "dynamic-sparse", "tiny"],
+                   default="plain-grid")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the run, copy a buffer of this many MiB three times (a plain "
@@ -76,7 +80,7 @@ def cpu_baseline(model, C, seed, what="1 sweep of the full workload"):
     oracle.run(model, dec, uid, seed, x, 0, 1, burn_in=0)
     dt = time.perf_counter() - t0
     return {"value": C * (model.n + model.m) / dt, "unit": "updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": min(oracle.num_threads(), C), "kind": "oracle",
             "sample": f"{what}, {C} chains, {dt:.2f} s wall"}
 
 
@@ -108,6 +112,23 @@ def timed_sweeps(s, steps, stream, between=None):
     return total_ms, dual_ms, primal_ms, wall
 
 
+def time_log_v(s, stream, reps=20):
+    """Average time of one partition-function estimate (log V of every chain,
+    between the phases of a sweep); outside the timed sweeps."""
+    import torch
+    ms = 0.0
+    for _ in range(reps):
+        s.dual_phase()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        s.log_v()
+        b.record(stream)
+        s.primal_phase()
+        b.synchronize()
+        ms += a.elapsed_time(b)
+    return ms / reps
+
+
 def run_plain(args):
     import torch
     from paper_1611_06684_amd import workloads as W
@@ -123,6 +144,7 @@ def run_plain(args):
         s.dual_phase()
         s.primal_phase()
     total_ms, dual_ms, primal_ms, wall = timed_sweeps(s, steps, stream)
+    log_v_ms = time_log_v(s, stream)
     s.sync()
     s.close()
     updates = C * (model.n + model.m)
@@ -138,7 +160,8 @@ def run_plain(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"plain grid {side}x{side}, q=4, FP32 tables, {C} chains",
                    "nodes": model.n, "edges": model.m, "chains": C, "seed": seed,
-                   "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall},
+                   "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall,
+                   "log_v_ms": log_v_ms},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
                      "unit": "VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": DUAL_TRAFFIC_PLAIN, "kernel": "k_dual64<4,true,4>",
@@ -228,6 +251,54 @@ def run_dynamic(args):
     return out
 
 
+def run_tiny(args):
+    import torch
+    from paper_1611_06684_amd import workloads as W
+    from paper_1611_06684_amd.pdg import Sampler
+    steps = 100000 if args.steps is None else args.steps
+    warmup = 1000 if args.warmup is None else args.warmup
+    model = W.ising_grid(4, 4, seed=0)
+    C, seed = 1, 0
+    s = Sampler(model, C, seed=seed, burn_in=0)
+    s.init()
+    s.sweep(warmup)
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    a.record(stream)
+    s.sweep(steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = a.elapsed_time(b)
+    s.close()
+    out = {
+        "metric": "sweeps/s", "value": steps / (ms / 1e3), "unit": "sweeps/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "tiny: 4x4 binary grid, FP64, 1 chain",
+                   "nodes": model.n, "edges": model.m, "chains": C, "seed": seed,
+                   "updates_per_s": C * (model.n + model.m) * steps / (ms / 1e3),
+                   "wall_s": wall},
+        "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": None,
+                     "frac": None, "traffic": None, "kernel": "k_sweeps<2,1,true,true>"},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        dec = oracle.decompose(model)
+        x = oracle.init_state(model, C, seed)
+        n_cpu = 5000000
+        t0 = time.perf_counter()
+        oracle.run(model, dec, np.arange(1, model.m + 1, dtype=np.uint64), seed, x, 0, n_cpu, 0)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n_cpu / dt, "unit": "sweeps/s",
+                               "cores": min(oracle.num_threads(), C), "kind": "oracle",
+                               "sample": f"{n_cpu} sweeps of the same workload, {dt:.2f} s wall"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -235,7 +306,8 @@ def main():
               "chains would shard across GPUs with no per-sweep communication, but no "
               "multi-GPU run is part of this build.", file=sys.stderr)
         sys.exit(2)
-    out = run_plain(args) if args.workload == "plain-grid" else run_dynamic(args)
+    run = {"plain-grid": run_plain, "dynamic-sparse": run_dynamic, "tiny": run_tiny}
+    out = run[args.workload](args)
     print(json.dumps(out), flush=True)
     if args.copy_mib > 0:
         import torch

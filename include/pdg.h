@@ -145,6 +145,19 @@ pdg_status pdg_primal_phase(pdg_ctx *ctx);
  * theta of entry d = (a-1)(q_dst-1) + (b-1). */
 pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_t *d_theta_out);
 
+/* Log of the partition-function estimator of Sec. 5.2, one value per chain,
+ * into d_out: double [C].  Called between pdg_dual_phase and pdg_primal_phase
+ * (else PDG_ESTATE): x is the state the duals were drawn from and theta those
+ * duals, a draw of the joint once the chain has mixed.  V(x, theta) =
+ * p~(x) p~(theta) / p~(x, theta) has mean Z, and log V has mean log Z minus
+ * the mutual information of x and theta, so its average over sweeps and chains
+ * is a lower bound of log Z.  With the Lemma of Sec. 3, log V = log p~(x) -
+ * sum_i log p(x_i | theta), p~(x) = prod_i u_i(x_i) prod_e phi_e(x_src, x_dst)
+ * from the tables given at insert (kept by the library).  FP64 throughout; the
+ * per-chain sums are added in a fixed order (reproducible).  Enqueued on the
+ * context's stream; d_out is written when that work completes. */
+pdg_status pdg_log_v(pdg_ctx *ctx, double *d_out);
+
 /* Marginal estimates p(x_i = a) = count / samples into d_out: double
  * [n][q_max]; *h_samples (optional) = C x counted sweeps.  Synchronizes. */
 pdg_status pdg_get_marginals(pdg_ctx *ctx, double *d_out, int64_t *h_samples);

@@ -53,6 +53,7 @@ struct pdg_ctx {
     uint64_t *d_uid = nullptr;
     uint8_t *d_sq = nullptr;
     uint8_t *d_params = nullptr;
+    void *d_lphi = nullptr;  // [slot][QM][QM] log tables as given (float or double)
     uint32_t *d_ipos = nullptr;
     uint32_t *d_off = nullptr, *d_cnt = nullptr;
     uint32_t *d_pool = nullptr;
@@ -322,6 +323,65 @@ static void launch_primal_e(pdg_ctx *ctx, uint32_t t, int count)
     }
 }
 
+// Small graphs (up to 16 chains, at most kSmallWaves waves per phase): many
+// sweeps in one launch of k_sweeps.
+constexpr int64_t kSmallWaves = 32;
+constexpr int32_t kSmallSweepsPerLaunch = 4096;
+
+static bool small_waves(const pdg_ctx *ctx, int64_t *dw, int64_t *pw)
+{
+    if (ctx->LPI > 16) return false;
+    const int64_t P = 64 / ctx->LPI;
+    *dw = cdiv(ctx->hwm, P) * ctx->CB;
+    *pw = cdiv(cdiv(ctx->n, 4), P) * ctx->CB;
+    return *dw <= kSmallWaves && *pw <= kSmallWaves;
+}
+
+template <int QM, int LPI, bool UQ, bool E64>
+static void sweeps_t(pdg_ctx *ctx, uint32_t t0, int32_t n, int64_t dw, int64_t pw)
+{
+    const int64_t waves = std::max(dw, pw);
+    const unsigned threads = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(64, waves * 64));
+    k_sweeps<QM, LPI, UQ, E64><<<1, threads, 0, ctx->stream>>>(
+        make_graph(ctx), t0, n, ctx->cfg.burn_in, dw, pw);
+}
+
+template <int QM, bool UQ, bool E64>
+static void sweeps_q(pdg_ctx *ctx, uint32_t t0, int32_t n, int64_t dw, int64_t pw)
+{
+    switch (ctx->LPI) {
+    case 1: sweeps_t<QM, 1, UQ, E64>(ctx, t0, n, dw, pw); break;
+    case 8: sweeps_t<QM, 8, UQ, E64>(ctx, t0, n, dw, pw); break;
+    default: sweeps_t<QM, 16, UQ, E64>(ctx, t0, n, dw, pw); break;
+    }
+}
+
+template <bool UQ, bool E64>
+static void sweeps_u(pdg_ctx *ctx, uint32_t t0, int32_t n, int64_t dw, int64_t pw)
+{
+    switch (ctx->QM) {
+    case 2: sweeps_q<2, UQ, E64>(ctx, t0, n, dw, pw); break;
+    case 3: sweeps_q<3, UQ, E64>(ctx, t0, n, dw, pw); break;
+    case 4: sweeps_q<4, UQ, E64>(ctx, t0, n, dw, pw); break;
+    case 5: sweeps_q<5, UQ, E64>(ctx, t0, n, dw, pw); break;
+    case 6: sweeps_q<6, UQ, E64>(ctx, t0, n, dw, pw); break;
+    case 7: sweeps_q<7, UQ, E64>(ctx, t0, n, dw, pw); break;
+    default: sweeps_q<8, UQ, E64>(ctx, t0, n, dw, pw); break;
+    }
+}
+
+static void launch_sweeps(pdg_ctx *ctx, uint32_t t0, int32_t n, int64_t dw, int64_t pw)
+{
+    const bool e64 = ctx->cfg.precision == PDG_PRECISION_F64;
+    if (ctx->uq) {
+        if (e64) sweeps_u<true, true>(ctx, t0, n, dw, pw);
+        else sweeps_u<true, false>(ctx, t0, n, dw, pw);
+    } else {
+        if (e64) sweeps_u<false, true>(ctx, t0, n, dw, pw);
+        else sweeps_u<false, false>(ctx, t0, n, dw, pw);
+    }
+}
+
 static void launch_primal(pdg_ctx *ctx, uint32_t t, int count)
 {
     const bool e64 = ctx->cfg.precision == PDG_PRECISION_F64;
@@ -582,6 +642,23 @@ struct NonZeroU64 {
     __host__ __device__ bool operator()(const uint64_t &v) const { return v != 0; }
 };
 
+template <int QM>
+static void logv_q(pdg_ctx *ctx, const Graph &g, int64_t bn, int64_t be, double *pn, double *pe)
+{
+    const hipStream_t st = ctx->stream;
+    if (g.C > 32)
+        k_logv_nodes<QM, true><<<dim3((unsigned)bn, (unsigned)g.CB), 256, 0, st>>>(g, pn);
+    else
+        k_logv_nodes<QM, false><<<dim3((unsigned)bn, (unsigned)g.CB), 256, 0, st>>>(g, pn);
+    if (be == 0) return;
+    if (ctx->cfg.precision == PDG_PRECISION_F64)
+        k_logv_edges<QM, double><<<dim3((unsigned)be, (unsigned)g.CB), 256, 0, st>>>(
+            g, static_cast<const double *>(ctx->d_lphi), pe);
+    else
+        k_logv_edges<QM, float><<<dim3((unsigned)be, (unsigned)g.CB), 256, 0, st>>>(
+            g, static_cast<const float *>(ctx->d_lphi), pe);
+}
+
 static void free_all(pdg_ctx *ctx)
 {
     void *ps[] = {ctx->d_q,     ctx->d_lam,   ctx->d_x,     ctx->d_counts, ctx->d_src,
@@ -589,7 +666,7 @@ static void free_all(pdg_ctx *ctx)
                   ctx->d_off,   ctx->d_cnt,   ctx->d_pool,  ctx->d_rec_p,  ctx->d_rec_z,
                   ctx->d_flag,  ctx->d_scratch, ctx->d_base, ctx->d_hub, ctx->d_part,
                   ctx->d_free,  ctx->d_gen,   ctx->d_claim, ctx->d_cap,    ctx->d_nlive,
-                  ctx->d_mark,  ctx->d_sum};
+                  ctx->d_mark,  ctx->d_sum,   ctx->d_lphi};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -659,6 +736,8 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
         (s = dalloc(ctx, (void **)&ctx->d_uid, SP * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_sq, SP)) ||
         (s = dalloc(ctx, (void **)&ctx->d_params, SP * ctx->bbytes)) ||
+        (s = dalloc(ctx, &ctx->d_lphi,
+                    SP * ctx->QM * ctx->QM * (cfg->precision == PDG_PRECISION_F64 ? 8 : 4))) ||
         (s = dalloc(ctx, (void **)&ctx->d_ipos, SP * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_off, N4 * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_cnt, N4 * 4)) ||
@@ -841,6 +920,17 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     k_write_records<<<grid_for(m * ctx->RP), 256, 0, st>>>(m, ctx->QM, dslot, ctx->d_sq,
                                                            ctx->d_params, ctx->d_ipos,
                                                            ctx->d_rec_p);
+    {
+        const int32_t QQ = ctx->QM * ctx->QM;
+        if (ctx->cfg.precision == PDG_PRECISION_F64)
+            k_copy_tables<double><<<grid_for(m * QQ), 256, 0, st>>>(
+                m, QQ, dslot, static_cast<const double *>(d_log_phi),
+                static_cast<double *>(ctx->d_lphi));
+        else
+            k_copy_tables<float><<<grid_for(m * QQ), 256, 0, st>>>(
+                m, QQ, dslot, static_cast<const float *>(d_log_phi),
+                static_cast<float *>(ctx->d_lphi));
+    }
     launch_node_base(ctx, runs, nullptr, uniq);
     PDG_HIP(ctx, hipGetLastError());
     PDG_TRY(rebuild_hubs(ctx, hflag, hpieces, hidx, pidx, tmp, tb));
@@ -1036,6 +1126,27 @@ pdg_status pdg_sweep(pdg_ctx *ctx, int64_t n_sweeps)
 {
     if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
     if (n_sweeps < 0) return fail(ctx, PDG_EINVAL, "n_sweeps < 0");
+    int64_t dw = 0, pw = 0;
+    if (n_sweeps > 1 && ctx->nodes_set && ctx->phase == 0 && ctx->hwm > 0 &&
+        small_waves(ctx, &dw, &pw)) {
+        // small graph: batches of sweeps in one launch each (same draws)
+        PDG_TRY(set_dev(ctx));
+        while (n_sweeps > 0) {
+            const int32_t k = (int32_t)std::min<int64_t>(n_sweeps, kSmallSweepsPerLaunch);
+            if (ctx->t + k >= 0xFFFFFFFFll) return fail(ctx, PDG_ECAPACITY, "sweep counter exhausted");
+            const int64_t first = std::max<int64_t>(ctx->t + 1, ctx->cfg.burn_in + 1);
+            const int64_t counted = std::max<int64_t>(0, ctx->t + k - first + 1);
+            if (counted && (uint64_t)(ctx->counted + counted) * (uint64_t)ctx->C > 0xFFFFFFFFull)
+                return fail(ctx, PDG_ECAPACITY,
+                            "marginal counters would overflow; read and reset them");
+            launch_sweeps(ctx, (uint32_t)ctx->t, k, dw, pw);
+            PDG_HIP(ctx, hipGetLastError());
+            ctx->t += k;
+            ctx->counted += counted;
+            n_sweeps -= k;
+        }
+        return PDG_OK;
+    }
     for (int64_t k = 0; k < n_sweeps; ++k) {
         PDG_TRY(pdg_dual_phase(ctx));
         PDG_TRY(pdg_primal_phase(ctx));
@@ -1063,6 +1174,38 @@ pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_
                                                                d_theta_out);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PDG_OK;
+}
+
+pdg_status pdg_log_v(pdg_ctx *ctx, double *d_out)
+{
+    if (!ctx || !d_out) return fail(ctx, PDG_EINVAL, "null argument");
+    if (ctx->phase != 1) return fail(ctx, PDG_ESTATE, "log V is taken between the two phases");
+    PDG_TRY(set_dev(ctx));
+    const Graph g = make_graph(ctx);
+    const int64_t bn = cdiv(ctx->n, 16), be = cdiv(ctx->hwm, 4 * kLvEdges);
+    const int64_t rows = bn + be, row = (int64_t)g.CB * 64;
+    const int64_t nb = std::min<int64_t>(rows, 1024), chunk = cdiv(rows, nb);
+    void *sp;
+    PDG_TRY(scratch(ctx, (rows + nb + 1) * row * 8 + 256, &sp));
+    double *pn = static_cast<double *>(sp), *pe = pn + bn * row, *mid = pn + rows * row;
+    switch (ctx->QM) {
+    case 2: logv_q<2>(ctx, g, bn, be, pn, pe); break;
+    case 3: logv_q<3>(ctx, g, bn, be, pn, pe); break;
+    case 4: logv_q<4>(ctx, g, bn, be, pn, pe); break;
+    case 5: logv_q<5>(ctx, g, bn, be, pn, pe); break;
+    case 6: logv_q<6>(ctx, g, bn, be, pn, pe); break;
+    case 7: logv_q<7>(ctx, g, bn, be, pn, pe); break;
+    default: logv_q<8>(ctx, g, bn, be, pn, pe); break;
+    }
+    // node rows then edge rows, in row order: partial sums of nb ranges, then
+    // the ranges in order
+    k_logv_reduce<<<dim3((unsigned)nb, (unsigned)g.CB), 64, 0, ctx->stream>>>(rows, chunk, g.CB,
+                                                                              pn, mid);
+    double *fin = mid + nb * row;
+    k_logv_reduce<<<dim3(1, (unsigned)g.CB), 64, 0, ctx->stream>>>(nb, nb, g.CB, mid, fin);
+    PDG_HIP(ctx, hipMemcpyAsync(d_out, fin, (size_t)ctx->C * 8, hipMemcpyDeviceToDevice,
+                                ctx->stream));
     return PDG_OK;
 }
 

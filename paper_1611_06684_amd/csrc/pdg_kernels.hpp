@@ -227,11 +227,15 @@ struct LaneMap {
     int c;         // chain
     int cb;        // chain block (LPI chains)
     __device__ __forceinline__ LaneMap(int32_t C)
+        : LaneMap(C, (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6))
+    {
+    }
+    // wave: index of this wave in the launch's item order
+    __device__ __forceinline__ LaneMap(int32_t C, int64_t wave)
     {
         constexpr int P = 64 / LPI;
         lane = threadIdx.x & 63;
-        const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
-                             __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int CB = (C + LPI - 1) / LPI;
         const int64_t group = (CB == 1) ? wave : wave / CB;
         cb = (int)(wave - group * CB);
@@ -289,14 +293,13 @@ __device__ __forceinline__ void count_quad(uint32_t *__restrict__ counts, int64_
 // UQ: every node has q_max states (compile-time entry loops).
 // ---------------------------------------------------------------------------
 template <int QM, int LPI, bool UQ>
-__global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
+__device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const LaneMap<LPI> lm)
 {
     static_assert(LPI <= 32, "33 or more chains: k_dual64");
     constexpr int D = dim_d(QM);
     constexpr int NCALL = (D + 4) / 5;
     constexpr int NW = (LPI == 32) ? 2 * D : 1;      // mask words gathered per wave
     constexpr int NREG = (NW + 63) / 64;
-    const LaneMap<LPI> lm(g.C);
     const int64_t slot = lm.item;
     const bool in_range = slot < g.hwm;
     const int64_t sl = in_range ? slot : 0;
@@ -412,6 +415,12 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
             }
         }
     }
+}
+
+template <int QM, int LPI, bool UQ>
+__global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
+{
+    dual_wave<QM, LPI, UQ>(g, t, LaneMap<LPI>(g.C));
 }
 
 // ---------------------------------------------------------------------------
@@ -1129,12 +1138,12 @@ __global__ __launch_bounds__(256) void k_hub_finish(Graph g, int64_t nh,
 // k_primal32 are the shapes for more chains.
 // ---------------------------------------------------------------------------
 template <int QM, int LPI, bool UQ, bool EXP64>
-__global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
+__device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int count,
+                                            const LaneMap<LPI> lm)
 {
     static_assert(LPI <= 16, "33 or more chains: k_primal64; 17..32: k_primal32");
     constexpr int D = dim_d(QM);
     constexpr int RP = rec_len(QM);
-    const LaneMap<LPI> lm(g.C);
     const int64_t quad = lm.item;
     const bool cvalid = lm.c < g.C;
     const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
@@ -1200,6 +1209,39 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
                     g.counts[node * QM + a] += (uint32_t)__popcll(mine);
             }
         }
+    }
+}
+
+template <int QM, int LPI, bool UQ, bool EXP64>
+__global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
+{
+    primal_wave<QM, LPI, UQ, EXP64>(g, t, count, LaneMap<LPI>(g.C));
+}
+
+// ---------------------------------------------------------------------------
+// Many sweeps of a small graph in one launch (up to 16 chains): one work-group
+// whose waves take the dual waves of a sweep in turn, meet at a barrier, take
+// the primal waves, and meet again.  The per-wave work is that of k_dual and
+// k_primal, so the trajectory is the one separate launches give; what goes
+// away is the launch latency, which bounds small graphs.  Sweeps t0 + 1 ..
+// t0 + n; counting from sweep burn_in + 1.
+// ---------------------------------------------------------------------------
+template <int QM, int LPI, bool UQ, bool EXP64>
+__global__ __launch_bounds__(1024) void k_sweeps(Graph g, uint32_t t0, int32_t n,
+                                                 int64_t burn_in, int64_t dual_waves,
+                                                 int64_t primal_waves)
+{
+    const int64_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nw = blockDim.x >> 6;
+    for (int32_t s = 0; s < n; ++s) {
+        const uint32_t t = t0 + 1u + (uint32_t)s;
+        for (int64_t v = w; v < dual_waves; v += nw)
+            dual_wave<QM, LPI, UQ>(g, t, LaneMap<LPI>(g.C, v));
+        __syncthreads();
+        const int count = (int64_t)t > burn_in ? 1 : 0;
+        for (int64_t v = w; v < primal_waves; v += nw)
+            primal_wave<QM, LPI, UQ, EXP64>(g, t, count, LaneMap<LPI>(g.C, v));
+        __syncthreads();
     }
 }
 
@@ -1321,6 +1363,183 @@ __global__ __launch_bounds__(256) void k_node_base(int64_t nn, const uint32_t *_
     for (int a = 1; a < QM; ++a)
         if (lane == a) v = acc[a];
     if (lane < QM) base[i * QM + lane] = lam[i * QM + lane] + v;
+}
+
+// New edges: keep their log tables (row = src state) for the estimator below.
+template <typename T>
+__global__ void k_copy_tables(int64_t m, int32_t QQ, const int32_t *__restrict__ slots,
+                              const T *__restrict__ phi, T *__restrict__ lphi)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * QQ) return;
+    const int64_t k = idx / QQ;
+    lphi[(int64_t)slots[k] * QQ + (idx - k * QQ)] = phi[idx];
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 5.2: the estimator V(x, theta) = p~(x) p~(theta) / p~(x, theta) of the
+// partition function.  By the Lemma of Sec. 3, p~(theta) / p~(x, theta) =
+// 1 / p(x | theta), which factorizes over the nodes, so per chain
+//   log V = sum_i lam_i(x_i) + sum_e Lam_e(x_src, x_dst)
+//           - sum_i [L_i(x_i) - log sum_a exp L_i(a)],
+// L_i the node field given theta (the primal phase's).  Evaluated between
+// the phases of a sweep, x being the state the duals were drawn from.  Lane =
+// chain; a block of four waves covers 16 nodes (a quad per wave) or 64 edges
+// (16 per wave) for one block of 64 chains and writes one row of partial sums
+// part[row][CB][64]; k_logv_reduce adds the rows of a chain in a fixed order,
+// so the value does not depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int kLvEdges = 16;  // edges per wave
+
+// Node part: lam_i(x_i) - log p(x_i | theta) over the block's 16 nodes.  Removed
+// edges leave zero records, which add nothing, so records are not tested.
+template <int QM, bool W64>
+__global__ __launch_bounds__(256) void k_logv_nodes(Graph g, double *__restrict__ part)
+{
+    constexpr int D = dim_d(QM);
+    constexpr int U = D <= 9 ? 2 : 1;  // records whose loads go out together
+    constexpr int ZS = W64 ? 2 : 1;    // u32 mask words between entries (64-bit words with C > 32)
+    __shared__ double red[4][64];
+    const int wib = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cb = blockIdx.y, c = cb * 64 + lane;
+    const bool cv = c < g.C;
+    const int64_t quad = (int64_t)blockIdx.x * 4 + wib;
+    // the quad's headers first
+    uint32_t off[4], cnt[4];
+    int xq[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = quad * 4 + j;
+        const bool in = i < g.n;
+        off[j] = in ? g.inc_off[i] : 0u;
+        cnt[j] = in ? g.inc_cnt[i] : 0u;
+        xq[j] = in && cv ? (int)g.x[i * g.C + c] : 0;
+    }
+    double acc = 0.0, zq = 1.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t i = quad * 4 + j;
+        if (i >= g.n) break;
+        const int qn = (int)g.q[i];
+        double L[QM];
+#pragma unroll
+        for (int a = 0; a < QM; ++a) L[a] = g.base[i * QM + a];  // finite past q_i
+        const uint32_t o = off[j], end = off[j] + cnt[j];
+        for (uint32_t r = o; r < end; r += U) {
+            // U records (clamped to the segment; extra ones add zero)
+            double hv[U][D];
+            uint32_t zw[U][D];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t rr = r + u < end ? r + u : end - 1;
+                const double *h = g.rec_p + (uint64_t)rr * D;
+                const uint32_t *z = g.rec_z + rec_zword(g, rr, 0, c, D);
+#pragma unroll
+                for (int dp = 0; dp < D; ++dp) {
+                    hv[u][dp] = h[dp];
+                    zw[u][dp] = z[dp * ZS];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (r + u >= end) break;
+#pragma unroll
+                for (int s = 1; s < QM; ++s)
+#pragma unroll
+                    for (int oo = 1; oo < QM; ++oo) {
+                        const int dp = (s - 1) * (QM - 1) + (oo - 1);
+                        // + 2 theta h: factor 0.0 or 2.0, 2h exact
+                        const double f = __hiloint2double(
+                            ((zw[u][dp] >> (c & 31)) & 1u) ? 0x40000000 : 0, 0);
+                        L[s] = __builtin_fma(f, hv[u][dp], L[s]);
+                    }
+            }
+        }
+        // log sum_a e^L(a) = mx + log z, z = 1 + sum over the other states of
+        // e^(L(a) - mx) in [1, q_i]; the z of the quad's nodes are multiplied
+        // and their log taken once
+        const int xi = xq[j];
+        double mx = L[0], lx = L[0];
+        int am = 0;
+#pragma unroll
+        for (int a = 1; a < QM; ++a) {
+            if (a < qn && L[a] > mx) {
+                mx = L[a];
+                am = a;
+            }
+            if (a == xi) lx = L[a];
+        }
+        double z = 1.0;
+#pragma unroll
+        for (int a = 0; a < QM; ++a)
+            if (a < qn && a != am) z += exp(L[a] - mx);
+        zq *= z;
+        acc += g.lam[i * QM + xi] - (lx - mx);
+    }
+    acc += log(zq);
+    red[wib][lane] = cv ? acc : 0.0;
+    __syncthreads();
+    if (wib == 0)
+        part[((int64_t)blockIdx.x * g.CB + cb) * 64 + lane] =
+            (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// Edge part: Lam_e(x_src, x_dst) over the block's 64 slots (free slots skipped),
+// from the log tables kept at insert.  A wave issues the loads of its 16
+// edges together.
+template <int QM, typename T>
+__global__ __launch_bounds__(256) void k_logv_edges(Graph g, const T *__restrict__ lphi,
+                                                    double *__restrict__ part)
+{
+    __shared__ double red[4][64];
+    const int wib = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cb = blockIdx.y, c = cb * 64 + lane;
+    const bool cv = c < g.C;
+    const int64_t e0 = ((int64_t)blockIdx.x * 4 + wib) * kLvEdges;
+    double acc = 0.0;
+    if (cv) {
+        int32_t sa[kLvEdges], da[kLvEdges];
+        bool live[kLvEdges];
+#pragma unroll
+        for (int k = 0; k < kLvEdges; ++k) {
+            const int64_t e = e0 + k;
+            live[k] = e < g.hwm && g.uid[e] != 0;
+            sa[k] = live[k] ? g.src[e] : 0;
+            da[k] = live[k] ? g.dst[e] : 0;
+        }
+        int xa[kLvEdges], xb[kLvEdges];
+#pragma unroll
+        for (int k = 0; k < kLvEdges; ++k) {
+            xa[k] = g.x[(int64_t)sa[k] * g.C + c];
+            xb[k] = g.x[(int64_t)da[k] * g.C + c];
+        }
+#pragma unroll
+        for (int k = 0; k < kLvEdges; ++k)
+            if (live[k]) acc += (double)lphi[((e0 + k) * QM + xa[k]) * QM + xb[k]];
+    }
+    red[wib][lane] = acc;
+    __syncthreads();
+    if (wib == 0)
+        part[((int64_t)blockIdx.x * g.CB + cb) * 64 + lane] =
+            (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// Rows [b chunk, (b + 1) chunk) of part[rows][CB][64] summed per chain into
+// out[b][CB][64] (block (b, cb), 64 threads; eight accumulators, fixed order).
+__global__ __launch_bounds__(64) void k_logv_reduce(int64_t rows, int64_t chunk, int32_t CB,
+                                                    const double *__restrict__ part,
+                                                    double *__restrict__ out)
+{
+    const int64_t b = blockIdx.x;
+    const int cb = blockIdx.y, l = threadIdx.x;
+    const int64_t k0 = b * chunk, k1 = k0 + chunk < rows ? k0 + chunk : rows;
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t k = k0;
+    for (; k + 8 <= k1; k += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += part[((k + u) * CB + cb) * 64 + l];
+    for (; k < k1; ++k) a[0] += part[(k * CB + cb) * 64 + l];
+    out[(b * CB + cb) * 64 + l] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 __global__ void k_marginals(int64_t nq, const uint32_t *__restrict__ counts, double inv,

@@ -27,7 +27,7 @@ EXPORTS = [
     "pdg_num_edges", "pdg_live_uids", "pdg_decompose", "pdg_params_layout", "pdg_init_chains",
     "pdg_set_state", "pdg_get_state", "pdg_get_sweep", "pdg_set_sweep", "pdg_sweep",
     "pdg_dual_phase", "pdg_primal_phase", "pdg_get_duals", "pdg_get_marginals",
-    "pdg_get_counts", "pdg_reset_marginals", "pdg_sync", "pdg_last_error",
+    "pdg_get_counts", "pdg_reset_marginals", "pdg_sync", "pdg_last_error", "pdg_log_v",
 ]
 
 
@@ -78,6 +78,7 @@ def lib():
             "pdg_dual_phase": ([_P], S),
             "pdg_primal_phase": ([_P], S),
             "pdg_get_duals": ([_P, _I64, _P, _P], S),
+            "pdg_log_v": ([_P, _P], S),
             "pdg_get_marginals": ([_P, _P, ctypes.POINTER(_I64)], S),
             "pdg_get_counts": ([_P, _P, ctypes.POINTER(_I64)], S),
             "pdg_reset_marginals": ([_P], S),
@@ -181,6 +182,10 @@ def pdg_primal_phase(ctx):
 
 def pdg_get_duals(ctx, m, d_uid, d_theta_out):
     _chk(lib().pdg_get_duals(ctx, m, d_uid, d_theta_out), ctx)
+
+
+def pdg_log_v(ctx, d_out):
+    _chk(lib().pdg_log_v(ctx, d_out), ctx)
 
 
 def pdg_get_marginals(ctx, d_out) -> int:
@@ -304,6 +309,12 @@ class Sampler:
     def duals(self, uids):
         out = self.torch.empty((len(uids), self.C), dtype=self.torch.int64, device=self.dev)
         pdg_get_duals(self.ctx, len(uids), uids.data_ptr(), out.data_ptr())
+        return out
+
+    def log_v(self):
+        """log V(x, theta) per chain (float64 [C]) between the two phases of a sweep."""
+        out = self.torch.empty(self.C, dtype=self.torch.float64, device=self.dev)
+        pdg_log_v(self.ctx, out.data_ptr())
         return out
 
     def marginals(self):

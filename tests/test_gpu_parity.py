@@ -131,6 +131,86 @@ def test_teacher_forced_sweeps(name, model, C):
     assert tot["flagged"] <= max(FLAG_BUDGET * tot["draws"], 3), tot
 
 
+
+def _log_v_tolerance(model, x, o):
+    """Bound on |GPU - oracle| for log V: both add the same N = n + m terms in
+    FP64 in different orders (error <= N 2^-53 of the sum of magnitudes each),
+    and the fields L differ by the rounding of two FP64 decompositions
+    (1e-13 of that sum is generous)."""
+    lam = np.asarray(model.lam, np.float64)
+    Lam = np.asarray(model.Lam, np.float64)
+    C = x.shape[1]
+    lp = np.zeros(C)
+    a_abs = np.zeros(C)
+    for c in range(C):
+        t1 = lam[np.arange(model.n), x[:, c]]
+        t2 = Lam[np.arange(model.m), x[model.src, c], x[model.dst, c]]
+        lp[c] = t1.sum() + t2.sum()
+        a_abs[c] = np.abs(t1).sum() + np.abs(t2).sum()
+    s_abs = a_abs + np.abs(o - lp)  # sum_i -log p(x_i | theta) >= 0
+    N = model.n + model.m
+    return 4 * N * 2.0 ** -53 * s_abs + 1e-13 * s_abs
+
+
+@pytest.mark.parametrize("name,model,C", list(_models()), ids=[m[0] for m in _models()])
+def test_log_v_matches_oracle(name, model, C):
+    """Sec. 5.2 estimator between the phases of a teacher-forced sweep: the
+    GPU's log V(x, theta) per chain against the oracle's on the same x and the
+    GPU's duals, for every kernel shape (hubs, chain blocks, mixed q)."""
+    import torch
+    seed = 4
+    s = _sampler(model, C, seed)
+    dec = oracle.decompose(model)
+    x_in = _random_state(model, C, 21)
+    s.t = 6
+    s.set_state(torch.as_tensor(x_in, device=s.dev))
+    s.dual_phase()
+    g = s.log_v().cpu().numpy()
+    th = _u64(s.duals(s.uids))
+    o = oracle.log_v(model, dec, th, x_in)
+    tol = _log_v_tolerance(model, x_in, o)
+    err = np.abs(g - o)
+    _say(f"  {name}: max |diff| {err.max():.3g}, max tol {tol.max():.3g}, log V ~ {o.mean():.4g}")
+    assert (err <= tol).all(), (err, tol)
+    s.primal_phase()
+    s.close()
+
+
+def test_log_v_mean_is_log_z_minus_mutual_information():
+    """Sec. 5.2 end to end on the GPU: on a 3x3 Ising model (12 duals, so the
+    joint can be enumerated) the average of log V over the sampler's sweeps and
+    64 chains equals log Z - I(x; theta) within 4 batch-means standard errors,
+    and stays below log Z."""
+    import torch
+    from tests import brute
+    model = W.ising_grid(3, 3, seed=41, J_half_range=0.6)
+    dec = oracle.decompose(model)
+    X, TH, P = brute.joint(model, dec)
+    lp = brute.log_joint(model, X)
+    log_Z = lp.max() + np.log(np.exp(lp - lp.max()).sum())
+    px, pth = P.sum(axis=1), P.sum(axis=0)
+    I = float((P * (np.log(P) - np.log(px)[:, None] - np.log(pth)[None, :])).sum())
+    target = log_Z - I
+    C = 64
+    s = _sampler(model, C, seed=3)
+    s.init()
+    s.sweep(200)
+    nb, per = 40, 100
+    means = []
+    for b in range(nb):
+        acc = torch.zeros(C, dtype=torch.float64, device=s.dev)
+        for _ in range(per):
+            s.dual_phase()
+            acc += s.log_v()
+            s.primal_phase()
+        means.append(acc.cpu().numpy().mean() / per)
+    means = np.array(means)
+    m, se = means.mean(), means.std(ddof=1) / np.sqrt(nb)
+    _say(f"  mean log V {m:.5f} +- {se:.5f}; log Z - I = {target:.5f}; log Z = {log_Z:.5f}; I = {I:.4f}")
+    assert abs(m - target) < 4 * se + 1e-6, (m, se, target)
+    assert m < log_Z
+    s.close()
+
 def test_init_is_bit_exact():
     for model, C, seed in [(W.random_graph(500, 10, [2, 3, 5, 8], seed=1), 37, 5),
                            (W.ising_grid(4, 4), 1, 0), (W.table_grid(30, 30, 4), 64, 2**40 + 3)]:
@@ -245,6 +325,37 @@ def test_fp64_free_running_trajectory_and_counts_exact():
         assert (cnt_g == cnt_o).all(), C
         s.close()
 
+
+
+def test_batched_small_sweeps_match_phase_launches():
+    """Small graphs run many sweeps in one launch (k_sweeps); the trajectory,
+    the counters (burn-in crossed inside a batch) and the sweep counter must be
+    those of one dual and one primal launch per sweep, bit for bit."""
+    import torch
+    from paper_1611_06684_amd import pdg
+    cases = [(W.random_graph(100, 200, [2, 3, 5], seed=51, dtype="f32"), 5, 7),
+             (W.random_graph(60, 120, [8], seed=52, dtype="f32"), 16, 0),
+             (W.ising_grid(4, 4, seed=53), 1, 3),
+             (W.random_graph(40, 90, [2, 4], seed=54), 12, 20)]
+    for model, C, burn in cases:
+        out = []
+        for batched in (True, False):
+            s = _sampler(model, C, seed=5, burn_in=burn)
+            s.init()
+            if batched:
+                s.sweep(25)
+            else:
+                for _ in range(25):
+                    s.dual_phase()
+                    s.primal_phase()
+            cnt = torch.zeros((model.n, model.q_max), dtype=torch.int32, device=s.dev)
+            samples = pdg.pdg_get_counts(s.ctx, cnt.data_ptr())
+            out.append((s.state().cpu().numpy(), cnt.cpu().numpy(), samples, s.t))
+            s.close()
+        (xa, ca, na, ta), (xb, cb, nb, tb) = out
+        _say(f"  {model.name} C={C}: samples {na} / {nb}, t {ta} / {tb}")
+        assert ta == tb == 25 and na == nb == C * (25 - burn)
+        assert np.array_equal(xa, xb) and np.array_equal(ca, cb)
 
 def test_tiny_marginals_vs_enumeration():
     """Tiny plain workload on the GPU: 4x4 binary grid, FP64, 1 chain, 1e5
@@ -469,6 +580,15 @@ def test_full_size_plain_grid_sampled():
     s.sweep(3)
     x_prev = s.state().cpu().numpy()
     s.dual_phase()
+    # Sec. 5.2 estimator at full size: log V of two chains against the oracle
+    lv = s.log_v().cpu().numpy()
+    th2 = np.ascontiguousarray(_u64(s.duals(s.uids))[:, :2])
+    dec_full = oracle.decompose(model)
+    o = oracle.log_v(model, dec_full, th2, np.ascontiguousarray(x_prev[:, :2]))
+    tol = _log_v_tolerance(model, np.ascontiguousarray(x_prev[:, :2]), o)
+    _say(f"[full-size] log V {lv[:2]} vs oracle {o}, tol {tol}")
+    assert (np.abs(lv[:2] - o) <= tol).all()
+    del th2, dec_full
     uids = _u64(s.uids)
     rng = np.random.default_rng(0)
     nodes = rng.choice(model.n, size=300, replace=False)
