@@ -283,7 +283,7 @@ def run_tiny(args):
                    "updates_per_s": C * (model.n + model.m) * steps / (ms / 1e3),
                    "wall_s": wall},
         "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": None,
-                     "frac": None, "traffic": None, "kernel": "k_sweeps<2,1,true,true>"},
+                     "frac": None, "traffic": None, "kernel": "k_sweeps_lds<2,true,true>"},
     }
     if not args.no_cpu_baseline:
         from oracle import oracle

@@ -370,8 +370,53 @@ static void sweeps_u(pdg_ctx *ctx, uint32_t t0, int32_t n, int64_t dw, int64_t p
     }
 }
 
+// Very small graphs (every edge-chain and node-chain pair one thread of one
+// work-group, q_max <= 5, state within 64 KB of LDS): k_sweeps_lds.
+static int64_t lds_bytes(const pdg_ctx *ctx)
+{
+    if (ctx->LPI > 16 || ctx->QM > 5) return -1;
+    if (ctx->hwm * ctx->C > 1024 || ctx->n * ctx->C > 1024) return -1;
+    const int64_t R = ctx->pool_top;  // bounds the entries in segments
+    const int64_t b = R * ctx->D * (8 + ctx->C) + ctx->n * (4 * ctx->QM + 4 + ctx->C) + 64;
+    return b <= 65536 ? b : -1;
+}
+
+template <int QM, bool UQ, bool E64>
+static void sweeps_lds_q(pdg_ctx *ctx, uint32_t t0, int32_t n, int64_t bytes)
+{
+    if constexpr (QM <= 5) {
+        const int64_t items = std::max(ctx->hwm, ctx->n) * ctx->C;
+        const unsigned threads = (unsigned)std::min<int64_t>(1024, cdiv(items, 64) * 64);
+        k_sweeps_lds<QM, UQ, E64><<<1, threads, (size_t)bytes, ctx->stream>>>(
+            make_graph(ctx), t0, n, ctx->cfg.burn_in, (uint32_t)ctx->pool_top);
+    }
+}
+
+template <bool UQ, bool E64>
+static void sweeps_lds_u(pdg_ctx *ctx, uint32_t t0, int32_t n, int64_t bytes)
+{
+    switch (ctx->QM) {
+    case 2: sweeps_lds_q<2, UQ, E64>(ctx, t0, n, bytes); break;
+    case 3: sweeps_lds_q<3, UQ, E64>(ctx, t0, n, bytes); break;
+    case 4: sweeps_lds_q<4, UQ, E64>(ctx, t0, n, bytes); break;
+    default: sweeps_lds_q<5, UQ, E64>(ctx, t0, n, bytes); break;
+    }
+}
+
 static void launch_sweeps(pdg_ctx *ctx, uint32_t t0, int32_t n, int64_t dw, int64_t pw)
 {
+    const int64_t bytes = lds_bytes(ctx);
+    if (bytes > 0) {
+        const bool e64 = ctx->cfg.precision == PDG_PRECISION_F64;
+        if (ctx->uq) {
+            if (e64) sweeps_lds_u<true, true>(ctx, t0, n, bytes);
+            else sweeps_lds_u<true, false>(ctx, t0, n, bytes);
+        } else {
+            if (e64) sweeps_lds_u<false, true>(ctx, t0, n, bytes);
+            else sweeps_lds_u<false, false>(ctx, t0, n, bytes);
+        }
+        return;
+    }
     const bool e64 = ctx->cfg.precision == PDG_PRECISION_F64;
     if (ctx->uq) {
         if (e64) sweeps_u<true, true>(ctx, t0, n, dw, pw);

@@ -1246,6 +1246,161 @@ __global__ __launch_bounds__(1024) void k_sweeps(Graph g, uint32_t t0, int32_t n
 }
 
 // ---------------------------------------------------------------------------
+// Many sweeps of a very small graph (every edge-chain and node-chain pair one
+// thread of one work-group, q_max <= 5) with the state in LDS: x, the dual
+// bits and the h records live in LDS and each thread keeps its edge's
+// thresholds and its node's base in registers, so a sweep costs two barriers
+// and no global memory round trip.  Draws and field sums are those of
+// k_dual / k_primal (same generator calls, same compares, same FMA order),
+// so the trajectory is bit-for-bit that of separate launches.  At the end x,
+// the counters and the last sweep's dual words go back to global memory.
+// LDS: h double [R][D] | counts u32 [n][QM] | pos u32 [n] | x u8 [n][C] |
+// theta u8 [R][D][C], R = the nodes' segment entries in node order.
+// ---------------------------------------------------------------------------
+template <int QM, bool UQ, bool EXP64>
+__global__ __launch_bounds__(1024) void k_sweeps_lds(Graph g, uint32_t t0, int32_t nsw,
+                                                     int64_t burn_in, uint32_t R)
+{
+    static_assert(QM <= 5, "thresholds kept in registers");
+    constexpr int D = dim_d(QM);
+    extern __shared__ __align__(16) uint8_t sm[];
+    const int n = (int)g.n, C = g.C, S = (int)g.hwm;
+    double *hl = reinterpret_cast<double *>(sm);
+    uint32_t *cl = reinterpret_cast<uint32_t *>(hl + (size_t)R * D);
+    uint32_t *pos = cl + (size_t)n * QM;
+    uint8_t *xl = reinterpret_cast<uint8_t *>(pos + n);
+    uint8_t *tl = xl + (size_t)n * C;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) {
+        uint32_t a = 0;
+        for (int i = 0; i < n; ++i) {
+            pos[i] = a;
+            a += g.inc_cnt[i];
+        }
+    }
+    for (int k = tid; k < n * C; k += nt) xl[k] = g.x[k];
+    for (int k = tid; k < n * QM; k += nt) cl[k] = 0u;
+    for (int k = tid; k < (int)R * D * C; k += nt) tl[k] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) {
+        const uint32_t o = g.inc_off[i], cn = g.inc_cnt[i], p0 = pos[i];
+        for (uint32_t k = 0; k < cn; ++k)
+            for (int dp = 0; dp < D; ++dp) hl[(size_t)(p0 + k) * D + dp] = g.rec_p[(uint64_t)(o + k) * D + dp];
+    }
+    // this thread's edge-chain item (dual) and node-chain item (primal)
+    const bool de = tid < S * C;
+    const int e = de ? tid / C : 0, ce = de ? tid % C : 0;
+    const uint64_t uid = de ? g.uid[e] : 0ull;
+    const bool dlive = uid != 0;
+    int src = 0, dst = 0, qs = QM, qd = QM;
+    uint32_t rs = 0, rd = 0;
+    uint64_t sign = 0;
+    uint32_t thr[2 * D];
+    if (dlive) {
+        src = g.src[e];
+        dst = g.dst[e];
+        if (!UQ) {
+            qs = (int)(g.sq[e] & 15u);
+            qd = (int)(g.sq[e] >> 4);
+        }
+    }
+    __syncthreads();  // pos and the h records complete
+    if (dlive) {
+        rs = pos[src] + (g.ipos[2 * (uint64_t)e] - g.inc_off[src]);
+        rd = pos[dst] + (g.ipos[2 * (uint64_t)e + 1] - g.inc_off[dst]);
+        const uint8_t *blk = g.params + (int64_t)e * block_bytes(QM);
+        sign = *reinterpret_cast<const uint64_t *>(blk);
+        const uint32_t *th = reinterpret_cast<const uint32_t *>(blk + off_thr(QM));
+#pragma unroll
+        for (int d = 0; d < 2 * D; ++d) thr[d] = th[d];
+    }
+    const bool dn = tid < n * C;
+    const int i = dn ? tid / C : 0, cn_ = dn ? tid % C : 0;
+    const int qn = dn ? (UQ ? QM : (int)g.q[i]) : QM;
+    double base[QM];
+#pragma unroll
+    for (int a = 0; a < QM; ++a) base[a] = dn && (UQ || a < qn) ? g.base[(int64_t)i * QM + a] : 0.0;
+    const uint32_t rp = dn ? pos[i] : 0u, rc = dn ? g.inc_cnt[i] : 0u;
+    const int De = UQ ? D : (qs - 1) * (qd - 1);
+    for (int sw = 0; sw < nsw; ++sw) {
+        const uint32_t t = t0 + 1u + (uint32_t)sw;
+        if (dlive) {
+            const int xs = xl[src * C + ce], xd = xl[dst * C + ce];
+#pragma unroll
+            for (int k = 0; k < (D + 4) / 5; ++k) {
+                if (5 * k >= De) break;
+                const Words w = philox4x32_10((uint32_t)uid, (uint32_t)(uid >> 32),
+                                              (kPhaseDual << 30) | (uint32_t)(16 * ce + k), t, g.rk);
+                const uint32_t W[5] = {w.w0, w.w1, w.w2, w.w3,
+                                       (w.w0 << 24) | ((w.w1 & 0xFFu) << 16) | ((w.w2 & 0xFFu) << 8)};
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    const int dd = 5 * k + j;
+                    if (dd >= De) break;
+                    const int a = dd / (qd - 1) + 1, b = dd % (qd - 1) + 1;
+                    const bool yh = (xs == a) != (((sign >> dd) & 1ull) != 0);
+                    const bool yb = xd == b;
+                    // theta = cp | (ch & (yh | y')) | (cm & yh & y'), as in k_dual
+                    const bool cp = W[j] > thr[2 * dd], cm = W[j] >= thr[2 * dd + 1];
+                    const bool ch = W[j] >= 0x80000000u;
+                    const uint8_t th = (uint8_t)(cp || (ch && (yh || yb)) || (cm && yh && yb));
+                    tl[((size_t)rs * D + (a - 1) * (QM - 1) + (b - 1)) * C + ce] = th;
+                    tl[((size_t)rd * D + (b - 1) * (QM - 1) + (a - 1)) * C + ce] = th;
+                }
+            }
+        }
+        __syncthreads();
+        if (dn) {
+            double L[QM];
+#pragma unroll
+            for (int a = 0; a < QM; ++a) L[a] = base[a];
+            for (uint32_t k = 0; k < rc; ++k) {
+                const double *h = hl + (size_t)(rp + k) * D;
+                const uint8_t *z = tl + (size_t)(rp + k) * D * C + cn_;
+#pragma unroll
+                for (int s = 1; s < QM; ++s) {
+                    if (!UQ && s >= qn) break;
+                    double acc = L[s];
+#pragma unroll
+                    for (int o = 1; o < QM; ++o) {
+                        const int dp = (s - 1) * (QM - 1) + (o - 1);
+                        acc = __builtin_fma(__hiloint2double(z[dp * C] ? 0x40000000 : 0, 0), h[dp], acc);
+                    }
+                    L[s] = acc;
+                }
+            }
+            const int64_t quad = i >> 2;
+            const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                           (kPhasePrimal << 30) | (uint32_t)cn_, t, g.rk);
+            const int xn = draw_node<QM, UQ, EXP64>(L, qn, word_at(wq, i & 3) >> 8);
+            xl[i * C + cn_] = (uint8_t)xn;
+            if ((int64_t)t > burn_in) atomicAdd(&cl[i * QM + xn], 1u);
+        }
+        __syncthreads();
+    }
+    for (int k = tid; k < n * C; k += nt) g.x[k] = xl[k];
+    for (int k = tid; k < n * QM; k += nt)
+        if (cl[k]) g.counts[k] += cl[k];
+    // the last sweep's dual words, in the records' global layout (entries
+    // [0, used) of the compact order belong to segments)
+    const uint32_t used = pos[n - 1] + g.inc_cnt[n - 1];
+    for (int k = tid; k < (int)used * D; k += nt) {
+        const uint32_t r = (uint32_t)(k / D);
+        const int dp = k - (int)r * D;
+        int lo = 0, hi = n - 1;  // node owning compact record r
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pos[mid] <= r) lo = mid; else hi = mid - 1;
+        }
+        const uint64_t pr = (uint64_t)g.inc_off[lo] + (r - pos[lo]);
+        uint32_t word = 0;
+        for (int c = 0; c < C; ++c)
+            if (tl[((size_t)r * D + dp) * C + c]) word |= 1u << c;
+        g.rec_z[rec_zword(g, pr, dp, 0, D)] = word;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Small kernels: edits, readout.
 // ---------------------------------------------------------------------------
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)

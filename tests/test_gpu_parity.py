@@ -328,7 +328,8 @@ def test_fp64_free_running_trajectory_and_counts_exact():
 
 
 def test_batched_small_sweeps_match_phase_launches():
-    """Small graphs run many sweeps in one launch (k_sweeps); the trajectory,
+    """Small graphs run many sweeps in one launch (k_sweeps, or k_sweeps_lds
+    with the state in LDS for the smallest); the trajectory,
     the counters (burn-in crossed inside a batch) and the sweep counter must be
     those of one dual and one primal launch per sweep, bit for bit."""
     import torch
@@ -336,7 +337,10 @@ def test_batched_small_sweeps_match_phase_launches():
     cases = [(W.random_graph(100, 200, [2, 3, 5], seed=51, dtype="f32"), 5, 7),
              (W.random_graph(60, 120, [8], seed=52, dtype="f32"), 16, 0),
              (W.ising_grid(4, 4, seed=53), 1, 3),
-             (W.random_graph(40, 90, [2, 4], seed=54), 12, 20)]
+             (W.random_graph(40, 90, [2, 4], seed=54), 12, 20),
+             # small enough for the LDS-resident form (q_max <= 5, one thread per item)
+             (W.random_graph(30, 50, [2, 3, 4], seed=55, dtype="f32"), 8, 4),
+             (W.ising_grid(6, 5, seed=56), 16, 10)]
     for model, C, burn in cases:
         out = []
         for batched in (True, False):
