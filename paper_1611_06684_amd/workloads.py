@@ -172,6 +172,57 @@ def random_graph(n: int, m: int, qs, seed: int = 0, pair_std: float = 0.5,
                  Lam.astype(dt), f"random_{n}_{m}")
 
 
+
+def batched_uneven(n_graphs: int, n_dense: int, seed: int = 0, n_min: int = 100,
+                   n_max: int = 50000, dense_n: int = 2048, dtype: str = "f32") -> Model:
+    """A batch of independent graphs as one model (disjoint union; node ids of
+    graph g start at meta["node_off"][g], its edges at meta["edge_off"][g]).
+    Sparse graphs: N ~ logU[n_min, n_max], mean degree d ~ U{3..12}, q ~ U{2,3,5}
+    per graph, N d / 2 endpoint pairs uniform within the graph (a self-loop's
+    dst moves to the next node), Lam ~ N(0, 0.2); dense graphs (the first
+    n_dense): complete binary graphs on dense_n nodes with Ising tables
+    J ~ N(0, 0.5 / sqrt(dense_n)); lam ~ N(0, 1) everywhere.  Draw order: per
+    graph in order, its size and q (sparse) then its edges, tables, unaries."""
+    rng = np.random.default_rng(seed)
+    dt = _np_dtype(dtype)
+    qm = 5
+    qs, lams, srcs, dsts, Lams = [], [], [], [], []
+    node_off, edge_off = [0], [0]
+    for g in range(n_graphs):
+        base = node_off[-1]
+        if g < n_dense:
+            N = dense_n
+            q = np.full(N, 2, np.int32)
+            iu, ju = np.triu_indices(N, 1)
+            J = rng.normal(0.0, 0.5 / np.sqrt(N), size=iu.shape[0])
+            s = np.array([-1.0, 1.0])
+            L = np.zeros((iu.shape[0], qm, qm))
+            L[:, :2, :2] = J[:, None, None] * s[None, :, None] * s[None, None, :]
+            src, dst = iu, ju
+        else:
+            N = int(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+            d = int(rng.integers(3, 13))
+            qg = int(rng.choice([2, 3, 5]))
+            q = np.full(N, qg, np.int32)
+            M = N * d // 2
+            src = rng.integers(0, N, size=M)
+            dst = rng.integers(0, N, size=M)
+            dst = np.where(src == dst, (dst + 1) % N, dst)
+            L = np.zeros((M, qm, qm))
+            L[:, :qg, :qg] = rng.normal(0.0, 0.2, size=(M, qg, qg))
+        lam = np.zeros((N, qm))
+        lam[:, :int(q[0])] = rng.normal(0.0, 1.0, size=(N, int(q[0])))
+        qs.append(q)
+        lams.append(lam)
+        srcs.append((src + base).astype(np.int32))
+        dsts.append((dst + base).astype(np.int32))
+        Lams.append(L.astype(dt))
+        node_off.append(base + N)
+        edge_off.append(edge_off[-1] + len(src))
+    return Model(np.concatenate(qs), np.concatenate(lams).astype(dt), np.concatenate(srcs),
+                 np.concatenate(dsts), np.concatenate(Lams), f"batch_{n_graphs}",
+                 {"node_off": np.array(node_off), "edge_off": np.array(edge_off)})
+
 class Churn:
     """Edge churn for dynamic graphs: each batch removes ``frac`` of the live
     edges uniformly without replacement and inserts as many new edges whose

@@ -81,6 +81,8 @@ def _models():
     yield "random_mixed_q678_f32_C40", W.random_graph(400, 1600, [6, 7, 8], seed=11, dtype="f32"), 40
     yield "grid_18x17_q6_f64_C64", W.table_grid(18, 17, 6, seed=12, dtype="f64"), 64
     # hubs: nodes with more incidences than a quad kernel takes (split into pieces)
+    # a batch of independent uneven graphs (mixed q per graph, two dense binary ones)
+    yield "batch_30_f32_C8", W.batched_uneven(30, 2, seed=1, n_min=20, n_max=300, dense_n=40), 8
     yield "hubs_q4_f32_C64", _hub_graph(900, [4], 3, 8), 64
     yield "hubs_mixed_q235_f32_C32", _hub_graph(700, [2, 3, 5], 4, 9), 32
     yield "hubs_q2_f32_C100", _hub_graph(600, [2], 2, 10), 100
