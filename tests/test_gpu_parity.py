@@ -497,6 +497,14 @@ def test_store_growth_relocation_and_relayout():
         _say(f"  {name}: live={len(live_uid)} deg(0)={deg0} {r}")
         assert r["bad_dual"] == 0 and r["bad_x"] == 0, r
         assert r["flagged"] <= FLAG_BUDGET * r["draws"] + 2, r
+        # the estimator reads the tables kept per slot: reused slots hold the new ones
+        a.t = 30 + rnd
+        a.set_state(torch.as_tensor(x_in, device=a.dev))
+        a.dual_phase()
+        lv = a.log_v().cpu().numpy()
+        o = oracle.log_v(cur, dec, _u64(a.duals(a.uids)), x_in)
+        assert (np.abs(lv - o) <= _log_v_tolerance(cur, x_in, o)).all(), (lv, o)
+        a.primal_phase()
     x0 = _random_state(model, C, 99)
     for s in (a, b):
         s.set_state(torch.as_tensor(x0, device=s.dev))
@@ -598,6 +606,9 @@ def test_error_paths():
         s.insert_edges([1, 2, 3], [2, 3, 4], np.zeros((3, 3, 3), np.float32))
     assert e.value.code == pdg.PDG_ECAPACITY
     assert pdg.pdg_num_edges(s.ctx) == 60
+    with pytest.raises(pdg.PdgError) as e:  # log V only between the phases
+        s.log_v()
+    assert e.value.code == pdg.PDG_ESTATE
     s.dual_phase()
     with pytest.raises(pdg.PdgError) as e:
         s.insert_edges([1], [2], np.zeros((1, 3, 3), np.float32))

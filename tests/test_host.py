@@ -1,0 +1,52 @@
+"""CPU checks of host-side logic: the workload generators' structure and the
+benchmark's one-GPU contract."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+from paper_1611_06684_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_batched_uneven_is_a_disjoint_union():
+    m = W.batched_uneven(12, 2, seed=3, n_min=20, n_max=200, dense_n=30)
+    no, eo = m.meta["node_off"], m.meta["edge_off"]
+    assert no[0] == 0 and no[-1] == m.n and eo[0] == 0 and eo[-1] == m.m
+    for g in range(12):
+        a, b = no[g], no[g + 1]
+        src, dst = m.src[eo[g]:eo[g + 1]], m.dst[eo[g]:eo[g + 1]]
+        # every edge stays inside its graph, no self-loops, one q per graph
+        assert ((src >= a) & (src < b) & (dst >= a) & (dst < b)).all()
+        assert (src != dst).all()
+        assert len(set(m.q[a:b].tolist())) == 1
+        qg = int(m.q[a])
+        L = m.Lam[eo[g]:eo[g + 1]]
+        assert not L[:, qg:, :].any() and not L[:, :, qg:].any()
+        if g < 2:  # dense binary graphs: complete, Ising tables
+            n = b - a
+            assert qg == 2 and len(src) == n * (n - 1) // 2
+            assert np.allclose(L[:, 0, 0], L[:, 1, 1]) and np.allclose(L[:, 0, 1], -L[:, 0, 0])
+        else:
+            assert qg in (2, 3, 5)
+    # unaries are zero past each node's states
+    beyond = np.arange(m.q_max)[None, :] >= m.q[:, None]
+    assert not m.lam[beyond].any()
+
+
+def test_batched_uneven_is_seeded():
+    a = W.batched_uneven(6, 1, seed=5, n_min=20, n_max=100, dense_n=12)
+    b = W.batched_uneven(6, 1, seed=5, n_min=20, n_max=100, dense_n=12)
+    for f in ("q", "lam", "src", "dst", "Lam"):
+        assert np.array_equal(getattr(a, f), getattr(b, f))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
