@@ -343,7 +343,7 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
         const Words w = philox4x32_10(ulo, uhi, (kPhaseDual << 30) | (uint32_t)(16 * lm.c + k), t,
                                       g.rk);
         const uint32_t W[5] = {w.w0, w.w1, w.w2, w.w3,
-                               (w.w0 << 24) | ((w.w1 & 0xFFu) << 16) | ((w.w2 & 0xFFu) << 8)};
+                               fifth_w(w)};
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             const int dd = 5 * k + j;
@@ -524,8 +524,7 @@ __global__ __launch_bounds__(256) void k_dual64(Graph g, uint32_t t)
                 const Words w = philox4x32_10(ulo, uhi, (kPhaseDual << 30) | (uint32_t)(16 * c + k),
                                               t, g.rk);
                 const uint32_t W[5] = {w.w0, w.w1, w.w2, w.w3,
-                                       (w.w0 << 24) | ((w.w1 & 0xFFu) << 16) |
-                                           ((w.w2 & 0xFFu) << 8)};
+                                       fifth_w(w)};
 #pragma unroll
                 for (int j = 0; j < 5; ++j) {
                     const int dd = 5 * k + j;
@@ -1332,7 +1331,7 @@ __global__ __launch_bounds__(1024) void k_sweeps_lds(Graph g, uint32_t t0, int32
                 const Words w = philox4x32_10((uint32_t)uid, (uint32_t)(uid >> 32),
                                               (kPhaseDual << 30) | (uint32_t)(16 * ce + k), t, g.rk);
                 const uint32_t W[5] = {w.w0, w.w1, w.w2, w.w3,
-                                       (w.w0 << 24) | ((w.w1 & 0xFFu) << 16) | ((w.w2 & 0xFFu) << 8)};
+                                       fifth_w(w)};
 #pragma unroll
                 for (int j = 0; j < 5; ++j) {
                     const int dd = 5 * k + j;

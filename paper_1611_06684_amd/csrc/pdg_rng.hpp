@@ -84,6 +84,16 @@ __device__ __forceinline__ uint32_t fifth_u24(const Words &w)
     return ((w.w0 & 0xFFu) << 16) | ((w.w1 & 0xFFu) << 8) | (w.w2 & 0xFFu);
 }
 
+// The fifth 24-bit integer in the top bits of a word, as the dual compares it:
+// bytes (high to low) w0.b0, w1.b0, w2.b0, 0, assembled by two byte
+// permutes (selector 0..3: bytes of the second operand, 4..7: of the first,
+// 12: zero).
+__device__ __forceinline__ uint32_t fifth_w(const Words &w)
+{
+    const uint32_t t = __builtin_amdgcn_perm(w.w1, w.w2, 0x0C04000Cu);  // 0, w1.b0, w2.b0, 0
+    return __builtin_amdgcn_perm(w.w0, t, 0x0402010Cu);                 // w0.b0, t.b2, t.b1, 0
+}
+
 // Word j (0..3) of a call, j runtime.
 __device__ __forceinline__ uint32_t word_at(const Words &w, int j)
 {
