@@ -213,6 +213,41 @@ def test_log_v_mean_is_log_z_minus_mutual_information():
     assert m < log_Z
     s.close()
 
+
+def _extreme_model(seed):
+    """Mixed-q random graph whose tables include odds ratios near 0 and infinity
+    (entries of size 30, so some thresholds saturate at 0 or 2^24) and tables
+    with every odds ratio exactly 1 (the dual is a fair coin that carries no
+    field), plus nodes without edges."""
+    m = W.random_graph(120, 200, [2, 3, 4], seed=seed, pair_std=1.0)
+    rng = np.random.default_rng(seed + 1)
+    Lam = m.Lam.copy()
+    for e in range(m.m):
+        qs, qd = int(m.q[m.src[e]]), int(m.q[m.dst[e]])
+        if e % 3 == 0:
+            Lam[e, :qs, :qd] = rng.choice([-30.0, 30.0], size=(qs, qd))
+        elif e % 3 == 1:  # rank one: L(a, b) = r(a) + c(b), every odds ratio 1
+            r, c = rng.normal(size=qs), rng.normal(size=qd)
+            Lam[e, :qs, :qd] = r[:, None] + c[None, :]
+    keep = (m.src < 100) & (m.dst < 100)  # nodes 100..119 keep no edge
+    return W.Model(m.q, m.lam, m.src[keep], m.dst[keep], Lam[keep], "extreme")
+
+
+@pytest.mark.parametrize("C", [3, 20, 64])
+def test_degenerate_tables_and_empty_graph(C):
+    """Edge cases of the method: saturated and unit odds ratios, isolated nodes,
+    and a graph with no edges at all (the primal then draws from the unaries),
+    each teacher-forced against the oracle for every kernel shape."""
+    for model in (_extreme_model(71), W.Model(*(lambda m: (m.q, m.lam, m.src[:0], m.dst[:0],
+                                                           m.Lam[:0]))(W.random_graph(50, 10, [2, 5], seed=72)))):
+        s = _sampler(model, C, seed=6)
+        dec = oracle.decompose(model)
+        x_in = _random_state(model, C, 73)
+        r = teacher_forced(s, model, dec, 6, x_in, 9)
+        _say(f"  {model.name} m={model.m} C={C}: {r}")
+        assert r["bad_dual"] == 0 and r["bad_x"] == 0, r
+        s.close()
+
 def test_init_is_bit_exact():
     for model, C, seed in [(W.random_graph(500, 10, [2, 3, 5, 8], seed=1), 37, 5),
                            (W.ising_grid(4, 4), 1, 0), (W.table_grid(30, 30, 4), 64, 2**40 + 3)]:
