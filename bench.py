@@ -14,9 +14,11 @@ Workloads (seeded, synthetic; recipes in workloads.py):
   tiny: 4 x 4 binary grid (Ising tables exp(J s s'), J ~ U(-0.3, 0.3), unaries
     exp(h s), h ~ N(0, 0.5)), FP64, one chain: bound by latency, so its line is
     sweeps/s (steps = sweeps, run in batches of one launch each).
-  batched: 512 independent graphs in one context (one launch per phase for all
-    of them): 504 sparse graphs with N ~ logU[100, 50000], mean degree U{3..12},
-    q ~ U{2,3,5}, plus 8 dense binary graphs on 2048 nodes; 8 chains.
+  batched: 512 independent graphs: 504 sparse graphs with N ~ logU[100, 50000],
+    mean degree U{3..12}, q ~ U{2,3,5}, plus 8 dense binary graphs on 2048 nodes;
+    8 chains.  By default one context per state count (one launch per phase for
+    all graphs with that count); --batch-layout one puts the whole batch in one
+    context.
 A step is one full sweep: the dual phase over every edge and chain, then the
 primal phase over every node and chain (with marginal counting).  The metric is
 chain * (|V| + |E|) updates/s with every input resident in HBM.
@@ -63,6 +65,10 @@ def parse():
     p.add_argument("--workload", choices=["plain-grid", "dynamic-sparse", "tiny", "batched"],
                    default="plain-grid")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--batch-layout", choices=["by-states", "one"], default="by-states",
+                   help="batched workload: one context per state count (records sized for "
+                        "that count) or one context for the whole batch (records sized for "
+                        "the largest)")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the run, copy a buffer of this many MiB three times (a plain "
                         "copy kernel of known size, to calibrate memory counters)")
@@ -302,6 +308,22 @@ def run_tiny(args):
     return out
 
 
+class SamplerGroup:
+    """Independent samplers on one stream, swept as one: a phase of the group is
+    that phase of every member, in order."""
+
+    def __init__(self, samplers):
+        self.samplers = samplers
+
+    def dual_phase(self):
+        for s in self.samplers:
+            s.dual_phase()
+
+    def primal_phase(self):
+        for s in self.samplers:
+            s.primal_phase()
+
+
 def run_batched(args):
     import torch
     from paper_1611_06684_amd import workloads as W
@@ -311,20 +333,31 @@ def run_batched(args):
     C, seed, n_graphs, n_dense = 8, 0, 512, 8
     log("building the batch")
     model = W.batched_uneven(n_graphs, n_dense, seed=0)
-    log(f"batch: {n_graphs} graphs, {model.n} nodes, {model.m} edges; uploading and decomposing")
-    s = Sampler(model, C, seed=seed, burn_in=0)
-    s.init()
+    if args.batch_layout == "by-states":
+        parts = W.group_by_states(model)
+    else:
+        parts = [(model.q_max, model)]
+    log(f"batch: {n_graphs} graphs, {model.n} nodes, {model.m} edges in "
+        f"{len(parts)} context(s); uploading and decomposing")
+    # distinct generator keys: the contexts' node and edge ids overlap
+    group = SamplerGroup([Sampler(p, C, seed=seed + k, burn_in=0)
+                          for k, (_, p) in enumerate(parts)])
+    for s in group.samplers:
+        s.init()
     for _ in range(warmup):
-        s.dual_phase()
-        s.primal_phase()
+        group.dual_phase()
+        group.primal_phase()
     stream = torch.cuda.current_stream()
-    total_ms, dual_ms, primal_ms, wall = timed_sweeps(s, steps, stream)
-    s.sync()
-    s.close()
+    total_ms, dual_ms, primal_ms, wall = timed_sweeps(group, steps, stream)
+    for s in group.samplers:
+        s.sync()
+        s.close()
     updates = C * (model.n + model.m)
     qs, qd = model.q[model.src], model.q[model.dst]
     draws = int(((qs - 1) * (qd - 1)).sum()) * C
     achieved = draws * DRAW_SLOTS / (dual_ms / 1e3)
+    kernels = ", ".join(f"k_dual<{q},8,{'true' if args.batch_layout == 'by-states' else 'false'}>"
+                        for q, _ in parts)
     out = {
         "metric": "chain*(|V|+|E|) updates/s", "value": updates * steps / (total_ms / 1e3),
         "unit": "updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -332,11 +365,13 @@ def run_batched(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"batched uneven: {n_graphs} graphs ({n_dense} dense binary "
                                f"N=2048), q in {{2,3,5}}, FP32 tables, {C} chains",
+                   "layout": (f"one context per state count ({len(parts)})"
+                              if args.batch_layout == "by-states" else "one context"),
                    "nodes": model.n, "edges": model.m, "chains": C, "seed": seed,
                    "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
                      "unit": "VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": None, "kernel": "k_dual<5,8,false>",
+                     "traffic": None, "kernel": kernels,
                      "work_per_draw_slots": DRAW_SLOTS},
     }
     if not args.no_cpu_baseline:

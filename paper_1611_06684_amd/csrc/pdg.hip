@@ -278,22 +278,29 @@ static void launch_dual(pdg_ctx *ctx, uint32_t t)
         launch_dual_u<false>(ctx, t);
 }
 
+template <int QM, int LPI, bool UQ, bool E64>
+static void hubs_t(pdg_ctx *ctx, const Graph &g, uint32_t t, int count, int64_t wp, int64_t wf,
+                   const uint32_t *hn, const uint32_t *hp, const uint32_t *pnode,
+                   const uint32_t *pf, const uint32_t *pn)
+{
+    k_hub_pieces<QM, LPI><<<grid_for(wp * 64), 256, 0, ctx->stream>>>(g, ctx->np, pnode, pf, pn,
+                                                                      ctx->d_part);
+    k_hub_finish<QM, UQ, E64, LPI><<<grid_for(wf * 64), 256, 0, ctx->stream>>>(
+        g, ctx->nh, hn, hp, ctx->d_part, t, count);
+}
+
 template <int QM, bool UQ, bool E64>
 static void launch_hubs_q(pdg_ctx *ctx, const Graph &g, uint32_t t, int count)
 {
     const uint32_t *hn = ctx->d_hub, *hp = hn + ctx->nh, *pnode = hp + ctx->nh + 1;
     const uint32_t *pf = pnode + ctx->np, *pn = pf + ctx->np;
     const int64_t wp = ctx->np * ctx->CB, wf = ctx->nh * ctx->CB;
-    if (ctx->LPI == 64) {
-        k_hub_pieces<QM, 64><<<grid_for(wp * 64), 256, 0, ctx->stream>>>(g, ctx->np, pnode, pf, pn,
-                                                                         ctx->d_part);
-        k_hub_finish<QM, UQ, E64, 64><<<grid_for(wf * 64), 256, 0, ctx->stream>>>(
-            g, ctx->nh, hn, hp, ctx->d_part, t, count);
-    } else {
-        k_hub_pieces<QM, 32><<<grid_for(wp * 64), 256, 0, ctx->stream>>>(g, ctx->np, pnode, pf, pn,
-                                                                         ctx->d_part);
-        k_hub_finish<QM, UQ, E64, 32><<<grid_for(wf * 64), 256, 0, ctx->stream>>>(
-            g, ctx->nh, hn, hp, ctx->d_part, t, count);
+    switch (ctx->LPI) {
+    case 1: hubs_t<QM, 1, UQ, E64>(ctx, g, t, count, wp, wf, hn, hp, pnode, pf, pn); break;
+    case 8: hubs_t<QM, 8, UQ, E64>(ctx, g, t, count, wp, wf, hn, hp, pnode, pf, pn); break;
+    case 16: hubs_t<QM, 16, UQ, E64>(ctx, g, t, count, wp, wf, hn, hp, pnode, pf, pn); break;
+    case 32: hubs_t<QM, 32, UQ, E64>(ctx, g, t, count, wp, wf, hn, hp, pnode, pf, pn); break;
+    default: hubs_t<QM, 64, UQ, E64>(ctx, g, t, count, wp, wf, hn, hp, pnode, pf, pn); break;
     }
 }
 
@@ -330,7 +337,8 @@ constexpr int32_t kSmallSweepsPerLaunch = 4096;
 
 static bool small_waves(const pdg_ctx *ctx, int64_t *dw, int64_t *pw)
 {
-    if (ctx->LPI > 16) return false;
+    // hubs are drawn by their own kernels, which the one-launch sweeps do not run
+    if (ctx->LPI > 16 || ctx->nh > 0) return false;
     const int64_t P = 64 / ctx->LPI;
     *dw = cdiv(ctx->hwm, P) * ctx->CB;
     *pw = cdiv(cdiv(ctx->n, 4), P) * ctx->CB;
@@ -633,20 +641,19 @@ static pdg_status full_relayout(pdg_ctx *ctx, int64_t runs, const uint32_t *uniq
 }
 
 // Hub list and piece table from the segment counts, in node order.  Hubs
-// are split only with 32 or more chains and while a hub piece kernel's LDS
-// chunk holds at least the records of one step.  flag / pieces / hidx /
+// are split only while a hub piece kernel's LDS chunk holds at least the
+// records of one step (one record per lane group).  flag / pieces / hidx /
 // pidx: scratch of n entries.
 static pdg_status rebuild_hubs(pdg_ctx *ctx, uint32_t *flag, uint32_t *pieces, uint32_t *hidx,
                                uint32_t *pidx, void *tmp, size_t tb)
 {
     ctx->hub_thr = 0;
     ctx->nh = ctx->np = 0;
-    if (ctx->LPI < 32) return PDG_OK;
     const int64_t D = ctx->D, RP = ctx->RP;
     const int64_t zr = ctx->LPI == 64 ? 2 * D * ctx->CB : D;
     const int64_t zb = (8 * D + 15) / 16 * 16;
     const int64_t K = (4096 - zb - 48) / (RP * 8 + 4 * zr);
-    if (K < (ctx->LPI == 32 ? 2 : 1)) return PDG_OK;
+    if (K < (ctx->LPI == 64 ? 1 : 64 / ctx->LPI)) return PDG_OK;
     const int64_t n = ctx->n;
     const hipStream_t st = ctx->stream;
     k_hub_count<<<grid_for(n), 256, 0, st>>>(n, ctx->d_cnt, kHubThreshold, kHubPiece, flag, pieces);

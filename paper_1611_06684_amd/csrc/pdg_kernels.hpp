@@ -980,9 +980,10 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
 // most kHubPiece so that one hub's work spreads over many waves.
 // k_hub_pieces: one wave per (piece, chain block) sums sum_records sum_o
 // 2 theta h over the piece (records staged in the wave's LDS region, the
-// chain's mask bit tested as in k_primal32); with LPI = 32 the halves take
-// alternate records and are added at the end.  The partial field goes to
-// part[((piece * CB + cb) * (QM - 1) + s - 1) * 64 + lane].
+// chain's mask bit tested as in k_primal32); with LPI <= 32 the 64 / LPI lane
+// groups take consecutive records of a step and are added at the end by a
+// butterfly (every lane ends with its chain's total, the same in every group).
+// The partial field goes to part[((piece * CB + cb) * (QM - 1) + s - 1) * 64 + lane].
 // k_hub_finish: one wave per (hub, chain block) adds the node's base and its
 // pieces' partial fields in piece order, then draws, stores x and counts.
 // ---------------------------------------------------------------------------
@@ -1012,12 +1013,13 @@ __global__ __launch_bounds__(256) void k_hub_pieces(Graph g, int64_t np,
     const uint32_t node = pnode[piece];
     const uint64_t r0 = (uint64_t)g.inc_off[node] + pfirst[piece];
     const uint32_t n = pn[piece];
-    const int p = LPI == 32 ? lane >> 5 : 0;
-    constexpr uint32_t PR = LPI == 32 ? 2u : 1u;                    // records per step
+    const int p = LPI == 64 ? 0 : lane / LPI;
+    constexpr uint32_t PR = LPI == 64 ? 1u : 64u / LPI;             // records per step
     const uint32_t zr = LPI == 64 ? 2u * D * (uint32_t)CB : (uint32_t)D;  // u32 words per record
     const uint32_t zsel = LPI == 64 ? (uint32_t)(cb * 2 * D + (lane >> 5)) : 0u;
     constexpr uint32_t ZSTEP = LPI == 64 ? 2u : 1u;
-    const uint32_t rot = (uint32_t)((lane & 31) + 2) & 31u;
+    const uint32_t cbit = LPI == 64 ? (uint32_t)(lane & 31) : (uint32_t)(lane % LPI);
+    const uint32_t rot = (cbit + 2u) & 31u;
     const uint32_t K = (uint32_t)(BUF - ZB - 48) / (uint32_t)(RP * 8 + 4 * zr);
     const uint32_t HB = (16 + K * (RP * 8) + 15) & ~15u;
     uint8_t *reg = lds[wib];
@@ -1049,8 +1051,8 @@ __global__ __launch_bounds__(256) void k_hub_pieces(Graph g, int64_t np,
         const double *hs = reinterpret_cast<const double *>(reg + sh);
         const uint32_t *zs = reinterpret_cast<const uint32_t *>(reg + HB + sz);
         for (uint32_t k = 0; k < nrec; k += PR) {
-            // with LPI = 32 half p takes record k + p; past the end it reads
-            // record k's h with an all-zero mask, which adds nothing
+            // lane group p takes record k + p; past the end it reads record
+            // k's h with an all-zero mask, which adds nothing
             const bool has = k + p < nrec;
             const double *h = hs + (has ? k + p : k) * RP;
             const uint32_t *z = has ? zs + (k + p) * zr + zsel : zero;
@@ -1068,9 +1070,10 @@ __global__ __launch_bounds__(256) void k_hub_pieces(Graph g, int64_t np,
             }
         }
     }
-    if (LPI == 32) {
 #pragma unroll
-        for (int s = 1; s < QM; ++s) L[s] += __shfl_xor(L[s], 32);
+    for (int sh = 32; sh >= LPI && sh > 0; sh >>= 1) {
+#pragma unroll
+        for (int s = 1; s < QM; ++s) L[s] += __shfl_xor(L[s], sh);
     }
 #pragma unroll
     for (int s = 1; s < QM; ++s)
@@ -1092,8 +1095,8 @@ __global__ __launch_bounds__(256) void k_hub_finish(Graph g, int64_t nh,
     const int cb = (int)(w - k * CB);
     if (k >= nh) return;
     const uint64_t node = hnode[k];
-    const int c = LPI == 64 ? cb * 64 + lane : (lane & 31);
-    const bool cvalid = c < g.C && (LPI == 64 || lane < 32);
+    const int c = LPI == 64 ? cb * 64 + lane : lane % LPI;
+    const bool cvalid = c < g.C && (LPI == 64 || lane < LPI);
     const int qn = UQ ? QM : (int)g.q[node];
     double L[QM];
 #pragma unroll
@@ -1151,11 +1154,13 @@ __device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int coun
     // segment table of the quad (the arrays are padded to a multiple of four
     // nodes; entries past n are zero)
     uint32_t off[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+    uint32_t hub = 0;  // bit j: node j is a hub (drawn by the hub kernels)
     if (quad * 4 < g.n) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             off[j] = g.inc_off[quad * 4 + j];
             cnt[j] = g.inc_cnt[quad * 4 + j];
+            if (g.heavy && cnt[j] > g.heavy) hub |= 1u << j;
         }
     }
     int newx[4], qnv[4];
@@ -1164,7 +1169,7 @@ __device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int coun
         const int64_t node = quad * 4 + j;
         newx[j] = -1;
         qnv[j] = 0;
-        if (node >= g.n) continue;
+        if (node >= g.n || ((hub >> j) & 1u)) continue;
         const int qn = UQ ? QM : (int)g.q[node];
         qnv[j] = qn;
         // the theta-free part (lam and every c0) is the node's base
@@ -1193,7 +1198,7 @@ __device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int coun
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t node = quad * 4 + j;
-        const bool nvalid = node < g.n;
+        const bool nvalid = node < g.n && !((hub >> j) & 1u);
         const bool active = nvalid && cvalid;
         if (active) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
         if (count) {

@@ -223,6 +223,35 @@ def batched_uneven(n_graphs: int, n_dense: int, seed: int = 0, n_min: int = 100,
                  np.concatenate(dsts), np.concatenate(Lams), f"batch_{n_graphs}",
                  {"node_off": np.array(node_off), "edge_off": np.array(edge_off)})
 
+def group_by_states(batch: Model) -> list:
+    """Splits a batch of independent graphs (``meta`` with ``node_off`` and
+    ``edge_off``, every node of a graph with the same state count) into one
+    model per state count q, tables cut to q x q and node ids renumbered
+    consecutively in graph order.  Returns [(q, model)] in increasing q; each
+    model's ``meta["graphs"]`` lists the batch's graph indices it holds and
+    ``meta["node_map"]`` / ``meta["edge_map"]`` the batch's node and edge index of
+    each of its nodes and edges.  The graphs do not interact, so sampling the
+    groups as separate models samples the batch."""
+    no, eo = batch.meta["node_off"], batch.meta["edge_off"]
+    gq = batch.q[no[:-1]]
+    out = []
+    for q in sorted(set(int(v) for v in gq)):
+        graphs = np.flatnonzero(gq == q)
+        nmap = np.concatenate([np.arange(no[g], no[g + 1]) for g in graphs]).astype(np.int64)
+        emap = np.concatenate([np.arange(eo[g], eo[g + 1]) for g in graphs]).astype(np.int64)
+        if np.any(batch.q[nmap] != q):
+            raise ValueError("a graph of the batch mixes state counts")
+        new_id = np.full(batch.n, -1, np.int64)
+        new_id[nmap] = np.arange(nmap.shape[0])
+        sub = Model(batch.q[nmap].copy(), np.ascontiguousarray(batch.lam[nmap, :q]),
+                    new_id[batch.src[emap]].astype(np.int32),
+                    new_id[batch.dst[emap]].astype(np.int32),
+                    np.ascontiguousarray(batch.Lam[emap, :q, :q]), f"{batch.name}_q{q}",
+                    {"graphs": graphs, "node_map": nmap, "edge_map": emap})
+        out.append((q, sub))
+    return out
+
+
 class Churn:
     """Edge churn for dynamic graphs: each batch removes ``frac`` of the live
     edges uniformly without replacement and inserts as many new edges whose

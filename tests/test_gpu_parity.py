@@ -83,9 +83,20 @@ def _models():
     # hubs: nodes with more incidences than a quad kernel takes (split into pieces)
     # a batch of independent uneven graphs (mixed q per graph, two dense binary ones)
     yield "batch_30_f32_C8", W.batched_uneven(30, 2, seed=1, n_min=20, n_max=300, dense_n=40), 8
+    # the same batch as one model per state count (uniform-q kernels, records of that q)
+    for q, g in W.group_by_states(W.batched_uneven(30, 2, seed=1, n_min=20, n_max=300,
+                                                   dense_n=40)):
+        yield f"batch_30_q{q}_f32_C8", g, 8
     yield "hubs_q4_f32_C64", _hub_graph(900, [4], 3, 8), 64
     yield "hubs_mixed_q235_f32_C32", _hub_graph(700, [2, 3, 5], 4, 9), 32
     yield "hubs_q2_f32_C100", _hub_graph(600, [2], 2, 10), 100
+    # hubs with 16 or fewer chains: 64 / LPI lane groups share a piece's records
+    yield "hubs_q2_f32_C1", _hub_graph(600, [2], 2, 10), 1
+    yield "hubs_mixed_q235_f32_C5", _hub_graph(700, [2, 3, 5], 4, 9), 5
+    yield "hubs_q4_f32_C16", _hub_graph(900, [4], 3, 8), 16
+    # q_max 8 with 8 chains: a step's records do not fit the piece kernel's
+    # LDS chunk, so hubs stay with the quad kernel
+    yield "hubs_q8_f32_C8", _hub_graph(500, [8], 2, 13), 8
 
 
 def _hub_graph(n, qs, n_hubs, seed):
@@ -789,3 +800,67 @@ def test_full_size_dynamic_sparse_sampled():
     _say(f"  sampled draws {n_draw}, flagged {n_flag}")
     assert n_flag <= max(FLAG_BUDGET * n_draw, 3)
     s.close()
+
+
+def test_full_size_batched_by_states_sampled():
+    """Batched workload at full size (512 graphs: 504 sparse with q in {2,3,5}, 8
+    dense binary on 2048 nodes; FP32 tables; 8 chains) in the layout the
+    benchmark times by default: one context per state count, distinct generator
+    seeds.  In each context: two sweeps from init, then one sweep whose sampled
+    nodes -- two nodes of dense graphs in the binary context, 2047 incidences
+    each -- and all their incident edges are checked one by one by the oracle."""
+    import torch
+    C = 8
+    _say("[batched full-size] building the batch")
+    batch = W.batched_uneven(512, 8, seed=0)
+    groups = W.group_by_states(batch)
+    del batch
+    rng = np.random.default_rng(0)
+    for k, (q, model) in enumerate(groups):
+        seed = k
+        _say(f"[batched full-size] q={q}: n={model.n} m={model.m}, seed {seed}")
+        s = _sampler(model, C, seed)
+        s.init()
+        s.sweep(2)
+        x_prev = s.state().cpu().numpy()
+        s.dual_phase()
+        uids = _u64(s.uids)
+        nodes = rng.choice(model.n, size=60, replace=False)
+        if q == 2:  # graphs 0..7 are the dense ones and come first
+            nodes = np.unique(np.concatenate([nodes, [5, 2048 * 7 + 100]]))
+        ends = np.concatenate([model.src, model.dst])
+        order = np.argsort(ends, kind="stable")
+        se = ends[order]
+        lo, hi = np.searchsorted(se, nodes), np.searchsorted(se, nodes, side="right")
+        inc = {int(i): order[a:b] for i, a, b in zip(nodes, lo, hi)}
+        edges = np.unique(np.concatenate(list(inc.values())) % model.m)
+        th_g = _u64(s.duals(torch.as_tensor(uids[edges].view(np.int64), device=s.dev)))
+        s.primal_phase()
+        x_new = s.state().cpu().numpy()
+        t = s.t
+        subm = model.subset_edges(edges)
+        dec = oracle.decompose(subm)
+        sub = {int(e): j for j, e in enumerate(edges)}
+        n_draw = n_flag = 0
+        for j, e in enumerate(edges):
+            for c in range(C):
+                th, fl = oracle.dual_edge(subm, dec, j, x_prev[model.src[e], c],
+                                          x_prev[model.dst[e], c], uids[e], c, t, seed)
+                assert ((int(th_g[j, c]) ^ th) & ~fl) == 0, (q, e, c)
+                n_draw += (q - 1) * (q - 1)
+                n_flag += bin(fl).count("1")
+        for i in nodes:
+            es = inc[int(i)]
+            sides = (es >= model.m).astype(np.int32)
+            rows = np.array([sub[int(e % model.m)] for e in es], dtype=np.int64)
+            for c in range(C):
+                xo, fo = oracle.primal_node(subm, dec, int(i), rows, sides,
+                                            [th_g[r, c] for r in rows], c, t, seed)
+                assert fo or xo == x_new[i, c], (q, i, c)
+                n_draw += 1
+                n_flag += fo
+        _say(f"  q={q}: {len(nodes)} nodes, {len(edges)} edges, sampled draws {n_draw}, "
+             f"flagged {n_flag}")
+        assert n_flag <= max(FLAG_BUDGET * n_draw, 3)
+        s.close()
+        del s

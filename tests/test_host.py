@@ -50,3 +50,32 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def _log_density(model, x):
+    """Unnormalised log-density of one state: unaries plus pairwise log-tables."""
+    e = np.arange(model.m)
+    return (model.lam[np.arange(model.n), x].astype(np.float64).sum()
+            + model.Lam[e, x[model.src], x[model.dst]].astype(np.float64).sum())
+
+
+def test_group_by_states_partitions_the_batch():
+    m = W.batched_uneven(14, 2, seed=7, n_min=20, n_max=150, dense_n=24)
+    groups = W.group_by_states(m)
+    assert [q for q, _ in groups] == sorted({int(v) for v in m.q})
+    nodes = np.concatenate([g.meta["node_map"] for _, g in groups])
+    edges = np.concatenate([g.meta["edge_map"] for _, g in groups])
+    assert np.array_equal(np.sort(nodes), np.arange(m.n))
+    assert np.array_equal(np.sort(edges), np.arange(m.m))
+    for q, g in groups:
+        nm, em = g.meta["node_map"], g.meta["edge_map"]
+        assert g.q_max == q and (g.q == q).all()
+        assert np.array_equal(nm[g.src], m.src[em]) and np.array_equal(nm[g.dst], m.dst[em])
+        assert np.array_equal(g.lam, m.lam[nm, :q])
+        assert np.array_equal(g.Lam, m.Lam[em, :q, :q])
+    # the batch's log-density is the sum of the groups' at every state
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        x = (rng.random(m.n) * m.q).astype(np.int64)
+        parts = sum(_log_density(g, x[g.meta["node_map"]]) for _, g in groups)
+        assert abs(_log_density(m, x) - parts) <= 1e-9 * (1 + abs(parts))
