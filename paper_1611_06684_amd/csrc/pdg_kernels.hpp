@@ -298,8 +298,15 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
     static_assert(LPI <= 32, "33 or more chains: k_dual64");
     constexpr int D = dim_d(QM);
     constexpr int NCALL = (D + 4) / 5;
-    constexpr int NW = (LPI == 32) ? 2 * D : 1;      // mask words gathered per wave
+    constexpr int P = 64 / LPI;                      // items (edge slots) per wave
+    // LPI >= 8 and records of 4 or more words: the mask words of the wave's P
+    // items are gathered into lanes p D + d and stored record by record (one
+    // contiguous run per record); otherwise the first lane of each item
+    // stores its words, with the record addresses loaded before the draws
+    constexpr bool GATHER = LPI >= 32 || (LPI >= 8 && D >= 4);
+    constexpr int NW = GATHER ? P * D : 1;
     constexpr int NREG = (NW + 63) / 64;
+    constexpr uint32_t WMASK = LPI >= 32 ? 0xFFFFFFFFu : (1u << LPI) - 1u;
     const int64_t slot = lm.item;
     const bool in_range = slot < g.hwm;
     const int64_t sl = in_range ? slot : 0;
@@ -363,10 +370,13 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
             const uint64_t ch = __ballot(W[j] >= 0x80000000u);   // U >= 2^23
             uint64_t zm = cp | (ch & (yh | yb)) | (cm & yh & yb);
             if (!UQ) zm &= __ballot(dd < De) & mact;
-            if (LPI == 32) {
-                outr[dd >> 6] = pdg_writelane_i32((uint32_t)zm, dd & 63, outr[dd >> 6]);
-                outr[(D + dd) >> 6] =
-                    pdg_writelane_i32((uint32_t)(zm >> 32), (D + dd) & 63, outr[(D + dd) >> 6]);
+            if (GATHER) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const int idx = p * D + dd;
+                    outr[idx >> 6] = pdg_writelane_i32((uint32_t)(zm >> (p * LPI)) & WMASK,
+                                                       idx & 63, outr[idx >> 6]);
+                }
             } else if (leader && (UQ || dd < De)) {
                 const int p0 = (lm.lane / LPI) * LPI;
                 const uint32_t wv = (uint32_t)((zm >> p0) & ((1ull << (LPI & 31)) - 1ull));
@@ -382,16 +392,17 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
             }
         }
     }
-    // LPI = 32: the gathered mask words go out to both records, each in its
+    // GATHER: the gathered mask words go out to both records, each in its
     // node's orientation: (a-1)(QM-1) + (b-1) in the src record, (b-1)(QM-1) +
-    // (a-1) in the dst record; lane p D + d holds item p's word of entry d.
+    // (a-1) in the dst record; lane p D + d of register r (index 64 r + lane)
+    // holds item p's word of entry d, so consecutive lanes fill one record.
     auto padded = [&](int dd, int qdv) -> int {
         return (dd / (qdv - 1)) * (QM - 1) + dd % (qdv - 1);
     };
     auto transposed = [&](int dd, int qdv) -> int {
         return (dd % (qdv - 1)) * (QM - 1) + dd / (qdv - 1);
     };
-    if (LPI == 32) {
+    if (GATHER) {
 #pragma unroll
         for (int r = 0; r < NREG; ++r) {
             const int idx = 64 * r + lm.lane;
