@@ -208,6 +208,10 @@ static void launch_dual_t(const Graph &g, uint32_t t, int CB, hipStream_t s)
         constexpr int E = kDualEdgesPerWave;
         const int64_t waves = cdiv(g.hwm, E) * CB;
         k_dual64<QM, UQ, E><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+    } else if constexpr (QM == 2 && (LPI == 8 || LPI == 16)) {
+        constexpr int P = 64 / LPI, E = kBinaryGroupsPerWave;
+        const int64_t waves = cdiv(cdiv(g.hwm, P), E);
+        k_dual_bin<LPI, UQ, E><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
     } else {
         constexpr int P = 64 / LPI;
         const int64_t waves = cdiv(g.hwm, P) * CB;
@@ -225,6 +229,11 @@ static void launch_primal_t(const Graph &g, uint32_t t, int count, int CB, hipSt
     } else if constexpr (LPI == 32) {
         const int64_t waves = cdiv(g.n, 4);  // one quad per wave, halves split the records
         k_primal32<QM, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
+    } else if constexpr ((LPI == 8 || LPI == 16) && QM >= 3) {
+        // records of 4 or more entries: staged once per wave (binary records
+        // are one word and one double; there the plain form is as fast)
+        const int64_t waves = cdiv(cdiv(g.n, 4), P) * CB;
+        k_primal_st<QM, LPI, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
     } else {
         const int64_t waves = cdiv(cdiv(g.n, 4), P) * CB;
         k_primal<QM, LPI, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);

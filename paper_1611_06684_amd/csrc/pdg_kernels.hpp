@@ -435,6 +435,93 @@ __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
 }
 
 // ---------------------------------------------------------------------------
+// a3 for binary records (q_max 2) with 8 or 16 chains: one draw per edge and
+// chain, so a wave of dual_wave is a chain of dependent loads (slot, endpoints,
+// their states) around a single generator call.  Here a wave takes E item
+// groups (E P consecutive slots) and issues the loads of all of them before
+// drawing, so E such chains are in flight per wave.  Draws, mask logic and
+// stores are dual_wave's (entry d = 0, value 0 of call (uid, DUAL, 16 c, t)).
+// ---------------------------------------------------------------------------
+constexpr int kBinaryGroupsPerWave = 4;
+
+template <int LPI, bool UQ, int E>
+__global__ __launch_bounds__(256) void k_dual_bin(Graph g, uint32_t t)
+{
+    static_assert(LPI == 8 || LPI == 16, "binary dual: 8 or 16 chains per item");
+    constexpr int P = 64 / LPI;
+    constexpr uint32_t WMASK = (1u << LPI) - 1u;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = lane % LPI;
+    const int pl = lane / LPI;
+    uint64_t uid[E];
+    int32_t es[E], ed[E];
+    uint32_t tp[E], tm[E], r0[E], r1[E];
+    bool neg[E];
+    int De[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t sl = (wave * E + e) * P + pl;
+        const bool in_range = sl < g.hwm;
+        uid[e] = in_range ? g.uid[sl] : 0ull;
+        const bool live = uid[e] != 0;
+        es[e] = 0;
+        ed[e] = 0;
+        tp[e] = 0;
+        tm[e] = 0;
+        r0[e] = 0;
+        r1[e] = 0;
+        neg[e] = false;
+        De[e] = 1;
+        if (live) {
+            es[e] = g.src[sl];
+            ed[e] = g.dst[sl];
+            const uint8_t *blk = g.params + sl * block_bytes(2);
+            neg[e] = (*reinterpret_cast<const uint64_t *>(blk) & 1ull) != 0;
+            const uint32_t *thr = reinterpret_cast<const uint32_t *>(blk + off_thr(2));
+            tp[e] = thr[0];
+            tm[e] = thr[1];
+            r0[e] = g.ipos[2 * sl];
+            r1[e] = g.ipos[2 * sl + 1];
+            if (!UQ) {
+                const uint32_t sq = g.sq[sl];
+                De[e] = ((int)(sq & 15u) - 1) * ((int)(sq >> 4) - 1);
+            }
+        }
+    }
+    int xs[E], xd[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        xs[e] = -1;
+        xd[e] = -1;
+        if (uid[e] != 0 && c < g.C) {
+            xs[e] = g.x[(int64_t)es[e] * g.C + c];
+            xd[e] = g.x[(int64_t)ed[e] * g.C + c];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const bool live = uid[e] != 0;
+        const bool active = live && c < g.C;
+        const Words w = philox4x32_10((uint32_t)uid[e], (uint32_t)(uid[e] >> 32),
+                                      (kPhaseDual << 30) | (uint32_t)(16 * c), t, g.rk);
+        const uint64_t ya = __ballot(xs[e] == 1), yb = __ballot(xd[e] == 1);
+        const uint64_t yh = ya ^ __ballot(neg[e]);
+        const uint64_t cp = __ballot(w.w0 > tp[e]);          // U >= T+
+        const uint64_t cm = __ballot(w.w0 >= tm[e]);         // U >= T-
+        const uint64_t ch = __ballot(w.w0 >= 0x80000000u);   // U >= 2^23
+        uint64_t zm = cp | (ch & (yh | yb)) | (cm & yh & yb);
+        if (!UQ) zm &= __ballot(0 < De[e]) & __ballot(active);
+        if (live && c == 0 && (UQ || De[e] > 0)) {
+            const uint32_t wv = (uint32_t)(zm >> (pl * LPI)) & WMASK;
+            g.rec_z[r0[e]] = wv;
+            g.rec_z[r1[e]] = wv;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // a3 with 33 or more chains: a wave takes E consecutive edge slots for one
 // block of 64 chains.  The slot metadata of all E edges comes in one batch of
 // scalar loads and their endpoint states in one batch of gathers; the
@@ -1231,6 +1318,172 @@ template <int QM, int LPI, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
 {
     primal_wave<QM, LPI, UQ, EXP64>(g, t, count, LaneMap<LPI>(g.C));
+}
+
+// ---------------------------------------------------------------------------
+// a4 + a5 with 8 or 16 chains per item on full launches: primal_wave's
+// arithmetic with each record loaded once per wave.  In primal_wave the LPI
+// lanes of an item all load the same words, so every load instruction moves
+// each byte LPI times.  Here step k of node j takes record k of node j of each
+// of the wave's P quads: its P h rows (D doubles) and P mask rows (D words) are
+// spread over the lanes, element e = 64 i + lane being entry e mod D of quad
+// e / D, loaded by one lane, written to the wave's LDS region (rows padded to
+// D + 1 elements, so the rows that one read touches fall in distinct banks) and
+// read back by the item's lanes as broadcasts.  The next step's elements are
+// loaded before the current step is summed.  The sums run in primal_wave's
+// order (records in order, entries in order), so states and counts are those
+// of primal_wave bit for bit.
+// ---------------------------------------------------------------------------
+template <int QM, int LPI, bool UQ, bool EXP64>
+__global__ __launch_bounds__(256) void k_primal_st(Graph g, uint32_t t, int count)
+{
+    static_assert(LPI == 8 || LPI == 16, "staged generic primal: 8 or 16 chains per item");
+    constexpr int D = dim_d(QM);
+    static_assert(rec_len(QM) == D, "one h per entry");
+    constexpr int P = 64 / LPI;      // quads per wave
+    constexpr int SH = D + 1;        // LDS row stride (elements)
+    constexpr int NE = P * D;        // elements per step
+    constexpr int NL = (NE + 63) / 64;
+    __shared__ double lh[4][P * SH];
+    __shared__ uint32_t lz[4][P * SH];
+    const LaneMap<LPI> lm(g.C);
+    const int lane = lm.lane;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *wh = lh[wib];
+    uint32_t *wz = lz[wib];
+    const int64_t quad = lm.item;
+    const int p = lane / LPI;
+    const bool cvalid = lm.c < g.C;
+    const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                   (kPhasePrimal << 30) | (uint32_t)lm.c, t, g.rk);
+    const uint32_t Wn[4] = {wq.w0, wq.w1, wq.w2, wq.w3};
+    uint32_t off[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+    uint32_t hub = 0;  // bit j: node j is a hub (drawn by the hub kernels)
+    if (quad * 4 < g.n) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            off[j] = g.inc_off[quad * 4 + j];
+            cnt[j] = g.inc_cnt[quad * 4 + j];
+            if (g.heavy && cnt[j] > g.heavy) {
+                hub |= 1u << j;
+                cnt[j] = 0;
+            }
+        }
+    }
+    // element e = 64 i + lane of a step: entry ede of quad epe (-1: none)
+    int epe[NL], ede[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int e = 64 * i + lane;
+        epe[i] = e < NE ? e / D : -1;
+        ede[i] = e < NE ? e - (e / D) * D : 0;
+    }
+    int newx[4], qnv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t node = quad * 4 + j;
+        const bool drawn = node < g.n && !((hub >> j) & 1u);
+        const int qn = UQ ? QM : (drawn ? (int)g.q[node] : 0);
+        newx[j] = -1;
+        qnv[j] = 0;
+        double L[QM];
+#pragma unroll
+        for (int a = 0; a < QM; ++a)
+            L[a] = (drawn && (UQ || a < qn)) ? g.base[node * QM + a] : 0.0;
+        // each element's record index (in elements) and record count, from
+        // the lanes of its quad
+        uint64_t eb[NL];
+        uint32_t ec[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int from = (epe[i] < 0 ? 0 : epe[i]) * LPI;
+            const uint32_t o = (uint32_t)__shfl((int)off[j], from);
+            const uint32_t n = (uint32_t)__shfl((int)cnt[j], from);
+            eb[i] = (uint64_t)o * D + (uint64_t)ede[i];
+            ec[i] = epe[i] < 0 ? 0u : n;
+        }
+        const uint32_t mine = cnt[j];  // records of this lane's node j (0: hub, padding)
+        double vh[NL];
+        uint32_t vz[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            vh[i] = 0.0;
+            vz[i] = 0u;
+            if (ec[i] > 0) {
+                vh[i] = g.rec_p[eb[i]];
+                vz[i] = g.rec_z[eb[i]];
+            }
+        }
+        for (uint32_t k = 0; __ballot(k < mine) != 0; ++k) {
+            double nh[NL];
+            uint32_t nz[NL];
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                nh[i] = 0.0;
+                nz[i] = 0u;
+                if (k + 1 < ec[i]) {
+                    nh[i] = g.rec_p[eb[i] + (uint64_t)(k + 1) * D];
+                    nz[i] = g.rec_z[eb[i] + (uint64_t)(k + 1) * D];
+                }
+            }
+            // the previous step's reads are issued before these writes (LDS
+            // operations of a wave complete in order)
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                if (epe[i] >= 0) {
+                    wh[epe[i] * SH + ede[i]] = vh[i];
+                    wz[epe[i] * SH + ede[i]] = vz[i];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (k < mine) {
+                const double *h = wh + p * SH;
+                const uint32_t *z = wz + p * SH;
+#pragma unroll
+                for (int s = 1; s < QM; ++s) {
+                    if (!UQ && s >= qn) break;
+                    double acc = L[s];
+#pragma unroll
+                    for (int o = 1; o < QM; ++o) {
+                        // acc + 2 theta h in one FMA: the factor is 0.0 or 2.0 and 2 h is exact
+                        const int dp = (s - 1) * (QM - 1) + (o - 1);
+                        const bool th = ((z[dp] >> (lm.c & 31)) & 1u) != 0;
+                        acc = __builtin_fma(__hiloint2double(th ? 0x40000000 : 0, 0), h[dp], acc);
+                    }
+                    L[s] = acc;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                vh[i] = nh[i];
+                vz[i] = nz[i];
+            }
+        }
+        if (drawn) {
+            qnv[j] = qn;
+            newx[j] = draw_node<QM, UQ, EXP64>(L, qn, Wn[j] >> 8);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t node = quad * 4 + j;
+        const bool nvalid = node < g.n && !((hub >> j) & 1u);
+        const bool active = nvalid && cvalid;
+        if (active) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
+        if (count) {
+            // one chain block: the lane group of the quad owns the node's counters
+            const bool leader = nvalid && (lane % LPI == 0);
+            const int p0 = p * LPI;
+#pragma unroll
+            for (int a = 0; a < QM; ++a) {
+                const uint64_t mine =
+                    (__ballot(active && newx[j] == a) >> p0) & ((1ull << LPI) - 1ull);
+                if (leader && a < qnv[j] && mine != 0)
+                    g.counts[node * QM + a] += (uint32_t)__popcll(mine);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -94,6 +94,9 @@ def _models():
     yield "hubs_q2_f32_C1", _hub_graph(600, [2], 2, 10), 1
     yield "hubs_mixed_q235_f32_C5", _hub_graph(700, [2, 3, 5], 4, 9), 5
     yield "hubs_q4_f32_C16", _hub_graph(900, [4], 3, 8), 16
+    # binary records with 16 and 3 chains (E item groups per wave, ragged)
+    yield "grid_21x19_q2_f32_C16", W.table_grid(21, 19, 2, seed=14), 16
+    yield "ising_9x7_f64_C3", W.ising_grid(9, 7, seed=15), 3
     # q_max 8 with 8 chains: a step's records do not fit the piece kernel's
     # LDS chunk, so hubs stay with the quad kernel
     yield "hubs_q8_f32_C8", _hub_graph(500, [8], 2, 13), 8
