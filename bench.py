@@ -55,6 +55,21 @@ DRAW_SLOTS = PHILOX_SLOTS / 5.0 + 3.0
 # WRITE_SIZE x 1 (factors from a 1 GiB copy), profiles/plain_grid_sweep_kernels.txt.
 # Measured for the kernel as it stands; it must be re-measured when the kernel changes.
 DUAL_TRAFFIC_PLAIN = 1031.1e6
+# HBM bytes of one batched dual phase in the per-state-count layout (the three
+# dual launches, q = 2, 3, 5), measured the same way,
+# profiles/batched_uneven_sweep_kernels.txt; re-measure when those kernels change.
+DUAL_TRAFFIC_BATCHED = 5046.0e6
+HBM_PEAK_GBS = 8000.0
+
+
+def dual_bytes(model, C):
+    """Algorithmic HBM bytes of one dual phase over `model` with C <= 32 chains
+    (records of 32-bit mask words): per edge with D = (q_src-1)(q_dst-1) entries,
+    slot metadata (uid 8, src 4, dst 4, record positions 8), the sign word (8) and
+    D threshold pairs (8 D), the endpoint states (2 C bytes) and the D mask words
+    written to each of the two records (8 D)."""
+    D = (model.q[model.src].astype(np.int64) - 1) * (model.q[model.dst] - 1)
+    return int((32 + 2 * C + 16 * D).sum())
 
 
 def parse():
@@ -353,11 +368,15 @@ def run_batched(args):
         s.sync()
         s.close()
     updates = C * (model.n + model.m)
-    qs, qd = model.q[model.src], model.q[model.dst]
-    draws = int(((qs - 1) * (qd - 1)).sum()) * C
-    achieved = draws * DRAW_SLOTS / (dual_ms / 1e3)
-    kernels = ", ".join(f"k_dual<{q},8,{'true' if args.batch_layout == 'by-states' else 'false'}>"
-                        for q, _ in parts)
+    by_states = args.batch_layout == "by-states"
+    # the dual phase (all its launches) against the HBM roof: its loads and
+    # stores are scattered over records and parameter blocks, and its VALU work
+    # (Philox) is a small fraction of the issue rate
+    alg = sum(dual_bytes(p, C) for _, p in parts)
+    achieved = alg / (dual_ms / 1e3) / 1e9
+    kernels = "dual phase: " + ", ".join(
+        ("k_dual_bin<8,true,4>" if q == 2 else f"k_dual<{q},8,true>") if by_states
+        else f"k_dual<{q},8,false>" for q, _ in parts)
     out = {
         "metric": "chain*(|V|+|E|) updates/s", "value": updates * steps / (total_ms / 1e3),
         "unit": "updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -369,10 +388,10 @@ def run_batched(args):
                               if args.batch_layout == "by-states" else "one context"),
                    "nodes": model.n, "edges": model.m, "chains": C, "seed": seed,
                    "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
-                     "unit": "VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": None, "kernel": kernels,
-                     "work_per_draw_slots": DRAW_SLOTS},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": DUAL_TRAFFIC_BATCHED if by_states else None,
+                     "algorithmic_bytes": alg, "kernel": kernels},
     }
     if not args.no_cpu_baseline:
         small = W.batched_uneven(16, 1, seed=0)
