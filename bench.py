@@ -54,11 +54,11 @@ DRAW_SLOTS = PHILOX_SLOTS / 5.0 + 3.0
 # HBM bytes per launch of k_dual64<4,true,4> on the plain grid: FETCH_SIZE x 2 +
 # WRITE_SIZE x 1 (factors from a 1 GiB copy), profiles/plain_grid_sweep_kernels.txt.
 # Measured for the kernel as it stands; it must be re-measured when the kernel changes.
-DUAL_TRAFFIC_PLAIN = 1031.1e6
+DUAL_TRAFFIC_PLAIN = 779.7e6
 # HBM bytes of one batched dual phase in the per-state-count layout (the three
 # dual launches, q = 2, 3, 5), measured the same way,
 # profiles/batched_uneven_sweep_kernels.txt; re-measure when those kernels change.
-DUAL_TRAFFIC_BATCHED = 5046.0e6
+DUAL_TRAFFIC_BATCHED = 3665.1e6
 HBM_PEAK_GBS = 8000.0
 
 

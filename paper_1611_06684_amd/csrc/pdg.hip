@@ -53,6 +53,7 @@ struct pdg_ctx {
     uint64_t *d_uid = nullptr;
     uint8_t *d_sq = nullptr;
     uint8_t *d_params = nullptr;
+    uint8_t *d_dparams = nullptr;  // [slot] sign word and thresholds of the block (thr_bytes)
     void *d_lphi = nullptr;  // [slot][QM][QM] log tables as given (float or double)
     uint32_t *d_ipos = nullptr;
     uint32_t *d_off = nullptr, *d_cnt = nullptr;
@@ -180,6 +181,7 @@ static Graph make_graph(pdg_ctx *ctx)
     g.uid = ctx->d_uid;
     g.sq = ctx->d_sq;
     g.params = ctx->d_params;
+    g.dparams = ctx->d_dparams;
     g.ipos = ctx->d_ipos;
     g.base = ctx->d_base;
     g.inc_off = ctx->d_off;
@@ -727,7 +729,7 @@ static void free_all(pdg_ctx *ctx)
                   ctx->d_off,   ctx->d_cnt,   ctx->d_pool,  ctx->d_rec_p,  ctx->d_rec_z,
                   ctx->d_flag,  ctx->d_scratch, ctx->d_base, ctx->d_hub, ctx->d_part,
                   ctx->d_free,  ctx->d_gen,   ctx->d_claim, ctx->d_cap,    ctx->d_nlive,
-                  ctx->d_mark,  ctx->d_sum,   ctx->d_lphi};
+                  ctx->d_mark,  ctx->d_sum,   ctx->d_lphi,  ctx->d_dparams};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -797,6 +799,7 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
         (s = dalloc(ctx, (void **)&ctx->d_uid, SP * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_sq, SP)) ||
         (s = dalloc(ctx, (void **)&ctx->d_params, SP * ctx->bbytes)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_dparams, SP * thr_bytes(ctx->QM))) ||
         (s = dalloc(ctx, &ctx->d_lphi,
                     SP * ctx->QM * ctx->QM * (cfg->precision == PDG_PRECISION_F64 ? 8 : 4))) ||
         (s = dalloc(ctx, (void **)&ctx->d_ipos, SP * 8)) ||
@@ -978,6 +981,11 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     PDG_TRY(clear_flag(ctx));
     launch_decompose(ctx->QM, ctx->cfg.precision == PDG_PRECISION_F64, m, dqs, dqd, d_log_phi,
                      dslot, ctx->d_params, ctx->d_flag, st);
+    {
+        const int32_t words = (int32_t)(thr_bytes(ctx->QM) / 4);
+        k_copy_dual_params<<<grid_for(m * words), 256, 0, st>>>(m, words, ctx->bbytes, dslot,
+                                                                ctx->d_params, ctx->d_dparams);
+    }
     k_write_records<<<grid_for(m * ctx->RP), 256, 0, st>>>(m, ctx->QM, dslot, ctx->d_sq,
                                                            ctx->d_params, ctx->d_ipos,
                                                            ctx->d_rec_p);

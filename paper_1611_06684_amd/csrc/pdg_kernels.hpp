@@ -61,6 +61,10 @@ __host__ __device__ constexpr int64_t block_bytes(int qm)
 {
     return 8 + 16 * (int64_t)dim_d(qm) + 16 * (int64_t)(qm - 1);
 }
+// The dual's part of a block: the sign word and the thresholds (its first
+// off_h bytes).  A context keeps it per slot in an array of its own as well,
+// so the dual kernels' lines carry no h or c0.
+__host__ __device__ constexpr int64_t thr_bytes(int qm) { return off_h(qm); }
 
 struct Graph {
     const uint8_t *__restrict__ q;        // [n] states per node
@@ -71,6 +75,7 @@ struct Graph {
     const uint64_t *__restrict__ uid;     // [slots], 0 = free slot
     const uint8_t *__restrict__ sq;       // [slots] q_src | q_dst << 4
     const uint8_t *__restrict__ params;   // [slots] parameter blocks
+    const uint8_t *__restrict__ dparams;  // [slots] their sign words and thresholds (thr_bytes)
     const uint32_t *__restrict__ ipos;    // [slots][2] record index per side
     const uint32_t *__restrict__ inc_off; // [n]
     const uint32_t *__restrict__ inc_cnt; // [n]
@@ -324,7 +329,7 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
         xs = g.x[(int64_t)g.src[sl] * g.C + lm.c];
         xd = g.x[(int64_t)g.dst[sl] * g.C + lm.c];
     }
-    const uint8_t *blk = g.params + sl * block_bytes(QM);
+    const uint8_t *blk = g.dparams + sl * thr_bytes(QM);
     const uint64_t sign = *reinterpret_cast<const uint64_t *>(blk);
     const uint32_t *thr = reinterpret_cast<const uint32_t *>(blk + off_thr(QM));
     const int De = UQ ? D : (qs - 1) * (qd - 1);
@@ -477,7 +482,7 @@ __global__ __launch_bounds__(256) void k_dual_bin(Graph g, uint32_t t)
         if (live) {
             es[e] = g.src[sl];
             ed[e] = g.dst[sl];
-            const uint8_t *blk = g.params + sl * block_bytes(2);
+            const uint8_t *blk = g.dparams + sl * thr_bytes(2);
             neg[e] = (*reinterpret_cast<const uint64_t *>(blk) & 1ull) != 0;
             const uint32_t *thr = reinterpret_cast<const uint32_t *>(blk + off_thr(2));
             tp[e] = thr[0];
@@ -577,20 +582,21 @@ __global__ __launch_bounds__(256) void k_dual64(Graph g, uint32_t t)
     }
     const uint64_t mact = __ballot(cvalid);
     auto load_params = [&](int64_t slot, DualParams<QM> &p) {
-        const uint8_t *blk = g.params + slot * block_bytes(QM);
+        const uint8_t *blk = g.dparams + slot * thr_bytes(QM);
         p.sign = *reinterpret_cast<const uint64_t *>(blk);
         const uint32_t *thr = reinterpret_cast<const uint32_t *>(blk + off_thr(QM));
 #pragma unroll
         for (int i = 0; i < 2 * D; ++i) p.thr[i] = thr[i];
     };
-    // touch the E parameter blocks (contiguous) with vector loads, all lines
-    // in flight at once, so the scalar loads of the edge loop hit L2
+    // touch the E edges' sign words and thresholds (contiguous) with vector
+    // loads, all lines in flight at once, so the scalar loads of the edge loop
+    // hit L2
     uint32_t sink;
     {
-        constexpr int64_t BB = block_bytes(QM);
+        constexpr int64_t BB = thr_bytes(QM);
         const uint64_t pb = (uint64_t)s0 * BB, pe = pb + (uint64_t)E * BB;
         const uint64_t pa = (pb & ~(uint64_t)127) + 128 * (uint64_t)lane;
-        sink = pa < pe ? *reinterpret_cast<const uint32_t *>(g.params + pa) : 0u;
+        sink = pa < pe ? *reinterpret_cast<const uint32_t *>(g.dparams + pa) : 0u;
     }
     // and the record indices, which the stores at the end read
     const uint32_t sink_ip = lane == 63 ? g.ipos[2 * s0] : 0u;
@@ -1576,7 +1582,7 @@ __global__ __launch_bounds__(1024) void k_sweeps_lds(Graph g, uint32_t t0, int32
     if (dlive) {
         rs = pos[src] + (g.ipos[2 * (uint64_t)e] - g.inc_off[src]);
         rd = pos[dst] + (g.ipos[2 * (uint64_t)e + 1] - g.inc_off[dst]);
-        const uint8_t *blk = g.params + (int64_t)e * block_bytes(QM);
+        const uint8_t *blk = g.dparams + (int64_t)e * thr_bytes(QM);
         sign = *reinterpret_cast<const uint64_t *>(blk);
         const uint32_t *th = reinterpret_cast<const uint32_t *>(blk + off_thr(QM));
 #pragma unroll
@@ -1789,6 +1795,19 @@ __global__ __launch_bounds__(256) void k_node_base(int64_t nn, const uint32_t *_
 }
 
 // New edges: keep their log tables (row = src state) for the estimator below.
+// Sign word and thresholds of the new edges' blocks into the dual's array
+// (words: thr_bytes / 4 per slot; bb: block bytes).
+__global__ void k_copy_dual_params(int64_t m, int32_t words, int64_t bb,
+                                   const int32_t *__restrict__ slots,
+                                   const uint8_t *__restrict__ params, uint8_t *__restrict__ dparams)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * words) return;
+    const int64_t k = idx / words, w = idx - k * words, sl = slots[k];
+    reinterpret_cast<uint32_t *>(dparams)[sl * words + w] =
+        *reinterpret_cast<const uint32_t *>(params + sl * bb + 4 * w);
+}
+
 template <typename T>
 __global__ void k_copy_tables(int64_t m, int32_t QQ, const int32_t *__restrict__ slots,
                               const T *__restrict__ phi, T *__restrict__ lphi)
