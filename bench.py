@@ -59,6 +59,9 @@ DUAL_TRAFFIC_PLAIN = 779.7e6
 # dual launches, q = 2, 3, 5), measured the same way,
 # profiles/batched_uneven_sweep_kernels.txt; re-measure when those kernels change.
 DUAL_TRAFFIC_BATCHED = 3665.1e6
+# and of one k_dual<8,32,true> launch on the dynamic workload,
+# profiles/dynamic_sparse_sweep_kernels.txt
+DUAL_TRAFFIC_DYNAMIC = 19355.1e6
 HBM_PEAK_GBS = 8000.0
 
 
@@ -94,16 +97,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(model, C, seed, what="1 sweep of the full workload"):
-    """The oracle, as it stands, on one sweep of `model` with C chains."""
+def cpu_baseline(model, C, seed, what="1 sweep of the full workload", sweeps=1):
+    """The oracle, as it stands, on `sweeps` sweeps of `model` with C chains."""
     from oracle import oracle
     dec = oracle.decompose(model)
     uid = np.arange(1, model.m + 1, dtype=np.uint64)
     x = oracle.init_state(model, C, seed)
     t0 = time.perf_counter()
-    oracle.run(model, dec, uid, seed, x, 0, 1, burn_in=0)
+    oracle.run(model, dec, uid, seed, x, 0, sweeps, burn_in=0)
     dt = time.perf_counter() - t0
-    return {"value": C * (model.n + model.m) / dt, "unit": "updates/s",
+    return {"value": C * (model.n + model.m) * sweeps / dt, "unit": "updates/s",
             "cores": min(oracle.num_threads(), C), "kind": "oracle",
             "sample": f"{what}, {C} chains, {dt:.2f} s wall"}
 
@@ -265,7 +268,7 @@ def run_dynamic(args):
                    "edit_batches_timed": sum(1 for k in range(steps) if (warmup + k) % every == 0)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
                      "unit": "VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": None, "kernel": "k_dual<8,32,true>",
+                     "traffic": DUAL_TRAFFIC_DYNAMIC, "kernel": "k_dual<8,32,true>",
                      "work_per_draw_slots": DRAW_SLOTS},
     }
     if not args.no_cpu_baseline:
@@ -396,7 +399,8 @@ def run_batched(args):
     if not args.no_cpu_baseline:
         small = W.batched_uneven(16, 1, seed=0)
         out["cpu_baseline"] = cpu_baseline(
-            small, C, seed, f"1 sweep of a 16-graph batch of the same recipe ({small.m} edges)")
+            small, C, seed, f"20 sweeps of a 16-graph batch of the same recipe ({small.m} edges)",
+            sweeps=20)
     return out
 
 
