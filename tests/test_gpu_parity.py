@@ -97,6 +97,13 @@ def _models():
     # binary records with 16 and 3 chains (E item groups per wave, ragged)
     yield "grid_21x19_q2_f32_C16", W.table_grid(21, 19, 2, seed=14), 16
     yield "ising_9x7_f64_C3", W.ising_grid(9, 7, seed=15), 3
+    # 2-16 chains with lanes of absent chains in every item, mixed and uniform
+    # q up to 8 (staged primal with several loads per step, gathered dual words)
+    yield "random_mixed_q258_f32_C9", W.random_graph(250, 600, [2, 5, 8], seed=21, dtype="f32"), 9
+    yield "random_mixed_q36_f64_C12", W.random_graph(250, 600, [3, 6], seed=22), 12
+    yield "random_q7_f32_C15", W.random_graph(200, 500, [7], seed=23, dtype="f32"), 15
+    yield "random_q4_f32_C7", W.random_graph(300, 700, [4], seed=24, dtype="f32"), 7
+    yield "random_mixed_q23_f32_C2", W.random_graph(300, 700, [2, 3], seed=25, dtype="f32"), 2
     # q_max 8 with 8 chains: a step's records do not fit the piece kernel's
     # LDS chunk, so hubs stay with the quad kernel
     yield "hubs_q8_f32_C8", _hub_graph(500, [8], 2, 13), 8
