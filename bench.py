@@ -195,7 +195,7 @@ def run_plain(args):
                      "work_per_draw_slots": DRAW_SLOTS},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(model, C, seed)
+        out["cpu_baseline"] = cpu_baseline(model, C, seed, "2 sweeps of the full workload", sweeps=2)
     return out
 
 
