@@ -1240,8 +1240,10 @@ __global__ __launch_bounds__(256) void k_hub_finish(Graph g, int64_t nh,
 // a record is stored in the node's own orientation (row = the node's state),
 // so both sides read the same way; padded entries and tombstones are zero.
 // Then the categorical draw of draw_node.  This generic form serves up to 16
-// chains (64 / LPI quads per wave, per-lane record loads); k_primal64 and
-// k_primal32 are the shapes for more chains.
+// chains (64 / LPI quads per wave, per-lane record loads): the one-launch
+// sweeps of small graphs, and full launches with one chain or binary records;
+// k_primal_st is the same arithmetic for 8 or 16 chains and larger records,
+// k_primal64 and k_primal32 the shapes for more chains.
 // ---------------------------------------------------------------------------
 template <int QM, int LPI, bool UQ, bool EXP64>
 __device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int count,
