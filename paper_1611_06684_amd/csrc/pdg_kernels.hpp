@@ -1572,6 +1572,8 @@ __global__ __launch_bounds__(1024) void k_sweeps_lds(Graph g, uint32_t t0, int32
     uint32_t rs = 0, rd = 0;
     uint64_t sign = 0;
     uint32_t thr[2 * D];
+#pragma unroll
+    for (int d = 0; d < 2 * D; ++d) thr[d] = 0u;
     if (dlive) {
         src = g.src[e];
         dst = g.dst[e];
@@ -1598,35 +1600,51 @@ __global__ __launch_bounds__(1024) void k_sweeps_lds(Graph g, uint32_t t0, int32
     for (int a = 0; a < QM; ++a) base[a] = dn && (UQ || a < qn) ? g.base[(int64_t)i * QM + a] : 0.0;
     const uint32_t rp = dn ? pos[i] : 0u, rc = dn ? g.inc_cnt[i] : 0u;
     const int De = UQ ? D : (qs - 1) * (qd - 1);
+    const int64_t quad = i >> 2;
+    // The generator words of a sweep do not depend on the state, so the next
+    // sweep's first dual call and its primal call are made while this sweep's
+    // node draw runs (straight-line code: both chains interleave); every lane
+    // computes them, and only the stores are predicated.
+    auto dual_call = [&](uint32_t t, int k) {
+        return philox4x32_10((uint32_t)uid, (uint32_t)(uid >> 32),
+                             (kPhaseDual << 30) | (uint32_t)(16 * ce + k), t, g.rk);
+    };
+    auto primal_call = [&](uint32_t t) {
+        return philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                             (kPhasePrimal << 30) | (uint32_t)cn_, t, g.rk);
+    };
+    Words wd = dual_call(t0 + 1u, 0), wq = primal_call(t0 + 1u);
     for (int sw = 0; sw < nsw; ++sw) {
         const uint32_t t = t0 + 1u + (uint32_t)sw;
-        if (dlive) {
+        {
             const int xs = xl[src * C + ce], xd = xl[dst * C + ce];
 #pragma unroll
             for (int k = 0; k < (D + 4) / 5; ++k) {
-                if (5 * k >= De) break;
-                const Words w = philox4x32_10((uint32_t)uid, (uint32_t)(uid >> 32),
-                                              (kPhaseDual << 30) | (uint32_t)(16 * ce + k), t, g.rk);
+                if (!UQ && 5 * k >= De) break;
+                const Words w = k == 0 ? wd : dual_call(t, k);
                 const uint32_t W[5] = {w.w0, w.w1, w.w2, w.w3,
                                        fifth_w(w)};
 #pragma unroll
                 for (int j = 0; j < 5; ++j) {
                     const int dd = 5 * k + j;
-                    if (dd >= De) break;
-                    const int a = dd / (qd - 1) + 1, b = dd % (qd - 1) + 1;
+                    if (dd >= D) break;
+                    const int qdv = UQ ? QM : (qd > 1 ? qd : 2);
+                    const int a = dd / (qdv - 1) + 1, b = dd % (qdv - 1) + 1;
                     const bool yh = (xs == a) != (((sign >> dd) & 1ull) != 0);
                     const bool yb = xd == b;
                     // theta = cp | (ch & (yh | y')) | (cm & yh & y'), as in k_dual
                     const bool cp = W[j] > thr[2 * dd], cm = W[j] >= thr[2 * dd + 1];
                     const bool ch = W[j] >= 0x80000000u;
                     const uint8_t th = (uint8_t)(cp || (ch && (yh || yb)) || (cm && yh && yb));
-                    tl[((size_t)rs * D + (a - 1) * (QM - 1) + (b - 1)) * C + ce] = th;
-                    tl[((size_t)rd * D + (b - 1) * (QM - 1) + (a - 1)) * C + ce] = th;
+                    if (dlive && (UQ || dd < De)) {
+                        tl[((size_t)rs * D + (a - 1) * (QM - 1) + (b - 1)) * C + ce] = th;
+                        tl[((size_t)rd * D + (b - 1) * (QM - 1) + (a - 1)) * C + ce] = th;
+                    }
                 }
             }
         }
         __syncthreads();
-        if (dn) {
+        {
             double L[QM];
 #pragma unroll
             for (int a = 0; a < QM; ++a) L[a] = base[a];
@@ -1645,12 +1663,14 @@ __global__ __launch_bounds__(1024) void k_sweeps_lds(Graph g, uint32_t t0, int32
                     L[s] = acc;
                 }
             }
-            const int64_t quad = i >> 2;
-            const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
-                                           (kPhasePrimal << 30) | (uint32_t)cn_, t, g.rk);
+            const Words wd_next = dual_call(t + 1u, 0), wq_next = primal_call(t + 1u);
             const int xn = draw_node<QM, UQ, EXP64>(L, qn, word_at(wq, i & 3) >> 8);
-            xl[i * C + cn_] = (uint8_t)xn;
-            if ((int64_t)t > burn_in) atomicAdd(&cl[i * QM + xn], 1u);
+            if (dn) {
+                xl[i * C + cn_] = (uint8_t)xn;
+                if ((int64_t)t > burn_in) atomicAdd(&cl[i * QM + xn], 1u);
+            }
+            wd = wd_next;
+            wq = wq_next;
         }
         __syncthreads();
     }
