@@ -79,3 +79,18 @@ def test_group_by_states_partitions_the_batch():
         x = (rng.random(m.n) * m.q).astype(np.int64)
         parts = sum(_log_density(g, x[g.meta["node_map"]]) for _, g in groups)
         assert abs(_log_density(m, x) - parts) <= 1e-9 * (1 + abs(parts))
+
+
+def test_dual_bytes_counts_each_edge_by_its_states():
+    """The batched roofline's algorithmic bytes: per edge 32 B of metadata and
+    sign word, 8 D of thresholds, 2 C of endpoint states and 8 D of mask words
+    written, with D = (q_src - 1)(q_dst - 1)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    q = np.array([2, 3, 5, 5], np.int32)
+    src = np.array([0, 1, 2, 0], np.int32)
+    dst = np.array([1, 2, 3, 3], np.int32)
+    m = W.Model(q, np.zeros((4, 5), np.float32), src, dst, np.zeros((4, 5, 5), np.float32))
+    C = 8
+    Ds = [1 * 2, 2 * 4, 4 * 4, 1 * 4]
+    assert bench.dual_bytes(m, C) == sum(32 + 2 * C + 16 * d for d in Ds)
