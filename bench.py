@@ -58,7 +58,7 @@ DUAL_TRAFFIC_PLAIN = 779.7e6
 # HBM bytes of one batched dual phase in the per-state-count layout (the three
 # dual launches, q = 2, 3, 5), measured the same way,
 # profiles/batched_uneven_sweep_kernels.txt; re-measure when those kernels change.
-DUAL_TRAFFIC_BATCHED = 3665.1e6
+DUAL_TRAFFIC_BATCHED = 3664.2e6
 # and of one k_dual<8,32,true> launch on the dynamic workload,
 # profiles/dynamic_sparse_sweep_kernels.txt
 DUAL_TRAFFIC_DYNAMIC = 19355.1e6

@@ -1342,8 +1342,10 @@ __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
 // order (records in order, entries in order), so states and counts are those
 // of primal_wave bit for bit.
 // ---------------------------------------------------------------------------
+// Uniform q up to 5: at most 80 VGPRs (six waves per SIMD) without spills.
 template <int QM, int LPI, bool UQ, bool EXP64>
-__global__ __launch_bounds__(256) void k_primal_st(Graph g, uint32_t t, int count)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UQ && QM <= 5 ? 6 : 1))) void k_primal_st(
+    Graph g, uint32_t t, int count)
 {
     static_assert(LPI == 8 || LPI == 16, "staged generic primal: 8 or 16 chains per item");
     constexpr int D = dim_d(QM);
