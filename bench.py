@@ -409,7 +409,7 @@ def main():
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler's "
               "chains would shard across GPUs with no per-sweep communication, but no "
-              "multi-GPU run is part of this build.", file=sys.stderr)
+              "multi-GPU path is implemented.", file=sys.stderr)
         sys.exit(2)
     run = {"plain-grid": run_plain, "dynamic-sparse": run_dynamic, "tiny": run_tiny,
            "batched": run_batched}
