@@ -1,16 +1,17 @@
 """Benchmark of the primal-dual Gibbs sweep on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--workload plain-grid|dynamic-sparse|tiny|batched]
+                    [--workload dynamic-sparse|plain-grid|tiny|batched]
 
 Workloads (seeded, synthetic; recipes in workloads.py):
-  plain-grid (default, the headline line): 1024 x 1024 open 4-neighbour grid,
-    q = 4, log-tables N(0, 0.2) per edge, log-unaries N(0, 1), FP32 tables, 64
-    independent chains, sampler seed 0.
-  dynamic-sparse: Chung-Lu power-law graph, 2^22 nodes, exponent 2.5, mean
-    degree 8, q = 8, log-tables N(0, 0.15), 32 chains; every 10 sweeps 1 % of the
-    live edges are removed and as many inserted (edit batches prepared on the
-    device before timing; the edits themselves are timed).
+  dynamic-sparse (default, the headline line: the largest single-GPU
+    configuration): Chung-Lu power-law graph, 2^22 nodes, exponent 2.5, mean
+    degree 8, q = 8, log-tables N(0, 0.15), log-unaries N(0, 1), FP32 tables,
+    32 chains; every 10 sweeps 1 % of the live edges are removed and as many
+    inserted (edit batches prepared on the device before timing; the edits
+    themselves are timed).
+  plain-grid: 1024 x 1024 open 4-neighbour grid, q = 4, log-tables N(0, 0.2)
+    per edge, log-unaries N(0, 1), FP32 tables, 64 independent chains.
   tiny: 4 x 4 binary grid (Ising tables exp(J s s'), J ~ U(-0.3, 0.3), unaries
     exp(h s), h ~ N(0, 0.5)), FP64, one chain: bound by latency, so its line is
     sweeps/s (steps = sweeps, run in batches of one launch each).
@@ -23,17 +24,23 @@ A step is one full sweep: the dual phase over every edge and chain, then the
 primal phase over every node and chain (with marginal counting).  The metric is
 chain * (|V| + |E|) updates/s with every input resident in HBM.
 
-Prints one JSON line.  ``roofline`` describes the dual-phase kernel: it is
-bound by integer VALU work (Philox draws), so achieved and peak are VALU issue
-slots per second; ``cpu_baseline`` is the FP64 oracle timed on the host cores
-on a bounded sample of the same workload.
+Prints one JSON line.  ``roofline`` describes the dominant kernel, the dual:
+it is bound by integer VALU work (Philox draws), so achieved and peak are VALU
+issue slots per second.  ``roofline_primal`` puts the primal phase against the
+HBM roof (algorithmic bytes: the h records and dual words of every incidence,
+per node its base row, state and counters).  ``traffic`` (HBM bytes per launch
+from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a plain copy) is read from the
+summary under profiles/ and is null when that summary was taken from other
+kernel sources than the ones built now.  ``cpu_baseline`` is the FP64 oracle
+timed on the host cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
+import subprocess
 import sys
 import time
 
@@ -51,18 +58,60 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 PHILOX_SLOTS = 10 * (2 + 2)
 DRAW_SLOTS = PHILOX_SLOTS / 5.0 + 3.0
-# HBM bytes per launch of k_dual64<4,true,4> on the plain grid: FETCH_SIZE x 2 +
-# WRITE_SIZE x 1 (factors from a 1 GiB copy), profiles/plain_grid_sweep_kernels.txt.
-# Measured for the kernel as it stands; it must be re-measured when the kernel changes.
-DUAL_TRAFFIC_PLAIN = 779.7e6
-# HBM bytes of one batched dual phase in the per-state-count layout (the three
-# dual launches, q = 2, 3, 5), measured the same way,
-# profiles/batched_uneven_sweep_kernels.txt; re-measure when those kernels change.
-DUAL_TRAFFIC_BATCHED = 3664.2e6
-# and of one k_dual<8,32,true> launch on the dynamic workload,
-# profiles/dynamic_sparse_sweep_kernels.txt
-DUAL_TRAFFIC_DYNAMIC = 19355.1e6
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+# what the path computes in (FP32-table workloads): FP64 decomposition and field
+# sums, FP32 exp in the node draw, 24-bit integer uniforms and thresholds
+DTYPE = "f64 fields + f32 exp + u32 draws"
+KERNEL_SOURCES = ["pdg_kernels.hpp", "pdg_rng.hpp", "pdg_store.hpp", "pdg.hip"]
+
+
+def kernel_digest():
+    """First 16 hex digits of the sha256 of the HIP sources the kernels are
+    built from (a profile summary records the digest it was taken with)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1611_06684_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profile_traffic(summary, label):
+    """HBM bytes per launch recorded under `label` in profiles/<summary>, as a line
+    ``traffic <label> <bytes> sources <digest>``; None when absent or taken from
+    other kernel sources."""
+    try:
+        text = open(os.path.join(PROFILES, summary)).read()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        f = line.split()
+        if len(f) == 5 and f[0] == "traffic" and f[1] == label and f[3] == "sources":
+            return float(f[2]) if f[4] == kernel_digest() else None
+    return None
+
+
+def host_info():
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return info
+
+
+def primal_bytes(model, C):
+    """Algorithmic HBM bytes of one primal phase with C <= 32 chains: per
+    incidence the record's h (8 D bytes, FP64) and its D dual words (4 D bytes,
+    one 32-bit chain mask per entry), D = (q_node - 1)(q_other - 1); per node its
+    base row (8 q_max), new states (C), counters read and written (8 q_max) and
+    segment offset and count (8)."""
+    D = (model.q[model.src].astype(np.int64) - 1) * (model.q[model.dst] - 1)
+    qm = model.q_max
+    return int(2 * (12 * D).sum() + model.n * (16 * qm + C + 8))
 
 
 def dual_bytes(model, C):
@@ -80,8 +129,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
-    p.add_argument("--workload", choices=["plain-grid", "dynamic-sparse", "tiny", "batched"],
-                   default="plain-grid")
+    p.add_argument("--workload", choices=["dynamic-sparse", "plain-grid", "tiny", "batched"],
+                   default="dynamic-sparse")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--batch-layout", choices=["by-states", "one"], default="by-states",
                    help="batched workload: one context per state count (records sized for "
@@ -97,9 +146,23 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _native_oracle():
+    """The oracle built for this host (-O3 -march=native); the portable build
+    when no compiler is at hand.  Returns the flags used."""
+    from oracle import oracle
+    try:
+        oracle.use_library(oracle.build_native())
+        return " ".join(oracle.FLAGS_NATIVE)
+    except (OSError, subprocess.CalledProcessError) as e:
+        log(f"native oracle build failed ({e}); timing the portable build")
+        oracle.use_library(None)
+        return " ".join(oracle.FLAGS)
+
+
 def cpu_baseline(model, C, seed, what="1 sweep of the full workload", sweeps=1):
     """The oracle, as it stands, on `sweeps` sweeps of `model` with C chains."""
     from oracle import oracle
+    flags = _native_oracle()
     dec = oracle.decompose(model)
     uid = np.arange(1, model.m + 1, dtype=np.uint64)
     x = oracle.init_state(model, C, seed)
@@ -108,7 +171,8 @@ def cpu_baseline(model, C, seed, what="1 sweep of the full workload", sweeps=1):
     dt = time.perf_counter() - t0
     return {"value": C * (model.n + model.m) * sweeps / dt, "unit": "updates/s",
             "cores": min(oracle.num_threads(), C), "kind": "oracle",
-            "sample": f"{what}, {C} chains, {dt:.2f} s wall"}
+            "sample": f"{what}, {C} chains, {dt:.2f} s wall",
+            "compile": flags, "host": host_info()}
 
 
 def timed_sweeps(s, steps, stream, between=None):
@@ -184,19 +248,68 @@ def run_plain(args):
         "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": total_ms / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": DTYPE, "data": "synthetic",
         "config": {"workload": f"plain grid {side}x{side}, q=4, FP32 tables, {C} chains",
                    "nodes": model.n, "edges": model.m, "chains": C, "seed": seed,
                    "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall,
                    "log_v_ms": log_v_ms},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
                      "unit": "VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": DUAL_TRAFFIC_PLAIN, "kernel": "k_dual64<4,true,4>",
+                     "traffic": profile_traffic("plain_grid_sweep_kernels.txt",
+                                                "k_dual64<4,true,4>"),
+                     "kernel": "k_dual64<4,true,4>",
                      "work_per_draw_slots": DRAW_SLOTS},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(model, C, seed, "2 sweeps of the full workload", sweeps=2)
     return out
+
+
+def dynamic_cpu_baseline(q, C, seed, every):
+    """The oracle on a bounded sample of the dynamic workload: the same recipe at
+    2^19 nodes (an eighth of the nodes and edges), one sweep of all C chains
+    followed by one churn step (1 % of the edges removed, as many inserted and
+    decomposed), then the same sweep with one chain on one core."""
+    from oracle import oracle
+    from paper_1611_06684_amd import workloads as W
+    n = 1 << 19
+    flags = _native_oracle()
+    model = W.chung_lu(n, q, seed=0)
+    dec = oracle.decompose(model)
+    churn = W.Churn(n, q, model.meta["weights"], seed=1)
+    uid = np.arange(1, model.m + 1, dtype=np.uint64)
+    x = oracle.init_state(model, C, seed)
+    t0 = time.perf_counter()
+    oracle.run(model, dec, uid, seed, x, 0, 1, burn_in=0)
+    t_sweep = time.perf_counter() - t0
+    rem, ns, nd, nL = churn.next_batch(uid)
+    keep = ~np.isin(uid, rem)
+    cur = W.Model(model.q, model.lam, np.concatenate([model.src[keep], ns]),
+                  np.concatenate([model.dst[keep], nd]), np.concatenate([model.Lam[keep], nL]))
+    new = oracle.decompose(W.Model(model.q, model.lam, ns, nd, nL))
+    dec2 = oracle.Decomposition(np.concatenate([dec.par[keep], new.par]),
+                                np.concatenate([dec.rrow[keep], new.rrow]),
+                                np.concatenate([dec.rcol[keep], new.rcol]))
+    uid2 = np.concatenate([uid[keep], uid[-1] + 1 + np.arange(len(ns), dtype=np.uint64)])
+    t_edit = time.perf_counter() - t0 - t_sweep
+    dt = time.perf_counter() - t0
+    ups = C * (model.n + model.m) / (t_sweep + t_edit / every)
+    threads = min(oracle.num_threads(), C)
+    oracle.set_threads(1)
+    x1 = np.ascontiguousarray(x[:, :1])
+    t1 = time.perf_counter()
+    oracle.run(cur, dec2, uid2, seed, x1, 1, 1, burn_in=0)
+    t_one = time.perf_counter() - t1
+    oracle.set_threads(threads)
+    oracle.use_library(None)
+    return {"value": ups, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": (f"the dynamic recipe at 2^19 nodes ({model.m} edges): 1 sweep of {C} "
+                       f"chains ({t_sweep:.2f} s) + 1 churn step of {len(ns)} removals and "
+                       f"insertions ({t_edit:.2f} s, charged as 1/{every} per sweep), "
+                       f"{dt:.1f} s wall"),
+            "single_core": {"value": (model.n + cur.m) / t_one, "unit": "updates/s",
+                            "sample": f"1 sweep of 1 chain on 1 thread, {t_one:.2f} s"},
+            "compile": flags, "host": host_info()}
 
 
 def run_dynamic(args):
@@ -250,9 +363,12 @@ def run_dynamic(args):
         s, steps, stream, between=lambda k: edit(warmup + k))
     s.sync()
     s.close()
+    del batches
     updates = C * (model.n + m_live)
     draws_per_launch = m_live * 49 * C
     achieved = draws_per_launch * DRAW_SLOTS / (dual_ms / 1e3)
+    pbytes = primal_bytes(model, C)
+    p_gbs = pbytes / (primal_ms / 1e3) / 1e9
     out = {
         "metric": "chain*(|V|+|E|) updates/s",
         "value": updates * steps / (total_ms / 1e3),
@@ -260,21 +376,29 @@ def run_dynamic(args):
         "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": total_ms / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": DTYPE, "data": "synthetic",
         "config": {"workload": f"dynamic sparse: Chung-Lu 2^22 nodes, q=8, FP32 tables, {C} chains, "
                                f"1% churn every {every} sweeps",
                    "nodes": model.n, "edges": m_live, "chains": C, "seed": seed,
                    "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall,
-                   "edit_batches_timed": sum(1 for k in range(steps) if (warmup + k) % every == 0)},
+                   "edit_batches_timed": sum(1 for k in range(steps) if (warmup + k) % every == 0),
+                   "kernel_sources": kernel_digest()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_LANE_OPS,
                      "unit": "VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": DUAL_TRAFFIC_DYNAMIC, "kernel": "k_dual<8,32,true>",
-                     "work_per_draw_slots": DRAW_SLOTS},
+                     "traffic": profile_traffic("dynamic_sparse_sweep_kernels.txt",
+                                                "k_dual<8,32,true>"),
+                     "kernel": "k_dual<8,32,true>", "work_per_draw_slots": DRAW_SLOTS,
+                     "units_per_launch": draws_per_launch},
+        "roofline_primal": {"bound": "hbm", "achieved": p_gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": p_gbs / HBM_PEAK_GBS,
+                            "traffic": profile_traffic("dynamic_sparse_sweep_kernels.txt",
+                                                       "primal_phase"),
+                            "kernel": "primal phase (k_primal32 + hub pieces + hub finish)",
+                            "algorithmic_bytes": pbytes},
     }
+    del model
     if not args.no_cpu_baseline:
-        small = W.chung_lu(1 << 18, q, seed=0)
-        out["cpu_baseline"] = cpu_baseline(
-            small, C, seed, f"1 sweep of the same recipe at 2^18 nodes ({small.m} edges)")
+        out["cpu_baseline"] = dynamic_cpu_baseline(q, C, seed, every)
     return out
 
 
@@ -384,7 +508,7 @@ def run_batched(args):
         "metric": "chain*(|V|+|E|) updates/s", "value": updates * steps / (total_ms / 1e3),
         "unit": "updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": total_ms / steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": DTYPE, "data": "synthetic",
         "config": {"workload": f"batched uneven: {n_graphs} graphs ({n_dense} dense binary "
                                f"N=2048), q in {{2,3,5}}, FP32 tables, {C} chains",
                    "layout": (f"one context per state count ({len(parts)})"
@@ -393,7 +517,8 @@ def run_batched(args):
                    "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": DUAL_TRAFFIC_BATCHED if by_states else None,
+                     "traffic": (profile_traffic("batched_uneven_sweep_kernels.txt", "dual_phase")
+                                 if by_states else None),
                      "algorithmic_bytes": alg, "kernel": kernels},
     }
     if not args.no_cpu_baseline:

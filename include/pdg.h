@@ -90,7 +90,13 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
 
 /* Remove m live edges by uid between sweeps (O(m) work on the device; the
  * freed slots are reused by later inserts under new uids).  Nothing is removed
- * if any uid is unknown or repeated (PDG_ENOTFOUND).  Synchronizes the stream. */
+ * if any uid is unknown or repeated (PDG_ENOTFOUND).  Synchronizes the stream.
+ *
+ * Failures of an edit after its checks have passed (a HIP error, or no memory
+ * for a re-layout of the incidence pool, in pdg_insert_edges or
+ * pdg_remove_edges) leave the edge store partly changed: the context then
+ * returns PDG_ESTATE from every later call that uses the device and must be
+ * destroyed.  Failures reported by the checks change nothing. */
 pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid);
 
 /* Number of live edges, and their uids in slot order (d_uid_out: uint64 [live]). */
@@ -124,7 +130,9 @@ pdg_status pdg_params_layout(int32_t q_max, int64_t *h_bytes_per_edge, int64_t *
 /* x(0) = floor(u q_i) for every node and chain (generator phase INIT);
  * resets the sweep counter to 0. */
 pdg_status pdg_init_chains(pdg_ctx *ctx);
-/* Copy a state in / out (uint8 [n][C]); pdg_set_state keeps the sweep counter. */
+/* Copy a state in / out (uint8 [n][C]); pdg_set_state keeps the sweep counter.
+ * pdg_set_state checks every x_i < q_i first (PDG_EINVAL and no change
+ * otherwise) and synchronizes the stream. */
 pdg_status pdg_set_state(pdg_ctx *ctx, const uint8_t *d_x);
 pdg_status pdg_get_state(pdg_ctx *ctx, uint8_t *d_x_out);
 /* Sweep counter: the last completed sweep t (0 after init).  pdg_set_sweep
@@ -159,7 +167,9 @@ pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_
 pdg_status pdg_log_v(pdg_ctx *ctx, double *d_out);
 
 /* Marginal estimates p(x_i = a) = count / samples into d_out: double
- * [n][q_max]; *h_samples (optional) = C x counted sweeps.  Synchronizes. */
+ * [n][q_max], one correctly rounded FP64 division per entry (0 before any
+ * counted sweep; entries a >= q_i are 0); *h_samples (optional) = C x counted
+ * sweeps.  Synchronizes. */
 pdg_status pdg_get_marginals(pdg_ctx *ctx, double *d_out, int64_t *h_samples);
 /* Raw counters uint32 [n][q_max]. */
 pdg_status pdg_get_counts(pdg_ctx *ctx, uint32_t *d_out, int64_t *h_samples);

@@ -23,13 +23,29 @@ PHASE_INIT, PHASE_DUAL, PHASE_PRIMAL = 0, 1, 2
 _lib = None
 
 
+LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+FLAGS = ["-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off"]
+# for timing on the host it runs on (CPU baseline): same source and arithmetic
+# (no contraction into FMA), tuned for that host's instruction set
+FLAGS_NATIVE = ["-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                "-ffp-contract=off"]
+
+
 def build() -> str:
     """Compile the oracle with gcc (portable -O2, OpenMP over chains)."""
     tmp = LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                           "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
+    subprocess.check_call(["gcc", *FLAGS, "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_native() -> str:
+    """Compile a copy for this host's CPU (-O3 -march=native) and return its path;
+    load it with use_library()."""
+    tmp = LIB_NATIVE + ".tmp"
+    subprocess.check_call(["gcc", *FLAGS_NATIVE, "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, LIB_NATIVE)
+    return LIB_NATIVE
 
 
 def use_library(path):
@@ -94,11 +110,17 @@ def _declare(L):
     L.orc_primal_phase.restype = ctypes.c_int
     L.orc_num_threads.argtypes = []
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_set_threads.argtypes = [_I32]
+    L.orc_set_threads.restype = None
     L.orc_all_logits.argtypes = [_I64, _I64, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_all_logits.restype = ctypes.c_int
     L.orc_log_v.argtypes = [_I64, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                             _P]
     L.orc_log_v.restype = ctypes.c_int
+    L.orc_dual_decide.argtypes = [_P, _I32, _I32, ctypes.c_double, _P]
+    L.orc_dual_decide.restype = ctypes.c_int
+    L.orc_categorical_draw.argtypes = [_I32, _P, ctypes.c_double, _P]
+    L.orc_categorical_draw.restype = _I32
 
 
 def _c(a, dtype):
@@ -141,6 +163,22 @@ def dual_p1(par5, y, yp) -> float:
     return lib().orc_dual_p1(pp, int(y), int(yp))
 
 
+def dual_decide(par5, y, yp, u):
+    """theta and flag of one dual draw with its uniform u given."""
+    p, pp = _c(par5, np.float64)
+    f = ctypes.c_int32(0)
+    th = lib().orc_dual_decide(pp, int(y), int(yp), float(u), ctypes.byref(f))
+    return int(th), int(f.value)
+
+
+def categorical_draw(L, u):
+    """State and flag of one node draw from logits L with its uniform u given."""
+    Lc, pl = _c(L, np.float64)
+    f = ctypes.c_int32(0)
+    x = lib().orc_categorical_draw(len(Lc), pl, float(u), ctypes.byref(f))
+    return int(x), int(f.value)
+
+
 class Decomposition:
     """Per-edge parameters: par [m][(q_max-1)^2][5] = (alpha1, alpha2, q, beta1, beta2),
     rrow/rcol [m][q_max] the unary parts carried by the src/dst endpoint."""
@@ -167,6 +205,10 @@ def decompose(model) -> Decomposition:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(k: int) -> None:
+    lib().orc_set_threads(int(k))
 
 
 # ------------------------------------------------------------------------ sweeps

@@ -226,6 +226,16 @@ void orc_init(int64_t n, int32_t C, const int32_t *q, uint64_t seed, uint8_t *x)
 /* sub = 16 c + floor(d/5), slot d % 5.  theta bit d = 1 iff u >= p(theta=0). */
 /* flag bit d set iff |u - p(theta=0)| < 1e-6.                                */
 /* ------------------------------------------------------------------------- */
+/* One dual given its uniform: p(theta = 0 | y, y') = 1 / (1 + exp(q + beta1 y +
+ * beta2 y')) from the Theorem's parameters p = (alpha1, alpha2, q, beta1, beta2);
+ * theta = 0 iff u < p(theta = 0).  *flag = [|u - p(theta = 0)| < 1e-6]. */
+int orc_dual_decide(const double *p, int32_t y, int32_t yp, double u, int32_t *flag)
+{
+    double p0 = 1.0 / (1.0 + exp(p[2] + p[3] * y + p[4] * yp));
+    *flag = fabs(u - p0) < ORC_FLAG_BAND;
+    return !(u < p0);
+}
+
 void orc_dual_edge(int32_t qi, int32_t qj, int32_t q_max, const double *par_e,
                    int32_t x_src, int32_t x_dst, uint64_t uid, int32_t c,
                    uint32_t t, uint64_t seed, uint64_t *theta_out, uint64_t *flag_out)
@@ -239,11 +249,10 @@ void orc_dual_edge(int32_t qi, int32_t qj, int32_t q_max, const double *par_e,
             if (d % 5 == 0)
                 orc_call(seed, ORC_PHASE_DUAL, uid, (uint32_t)(16 * c + d / 5), t, w);
             double u = orc_u24_to_unit(orc_u24(w, d % 5));
-            const double *p = par_e + (int64_t)d * 5;
             int y = (x_src == a), yp = (x_dst == b);
-            double p0 = 1.0 / (1.0 + exp(p[2] + p[3] * y + p[4] * yp));
-            if (!(u < p0)) th |= (1ull << d);
-            if (fabs(u - p0) < ORC_FLAG_BAND) fl |= (1ull << d);
+            int f = 0;
+            if (orc_dual_decide(par_e + (int64_t)d * 5, y, yp, u, &f)) th |= (1ull << d);
+            if (f) fl |= (1ull << d);
         }
     }
     *theta_out = th;
@@ -331,6 +340,15 @@ static int orc_categorical(int32_t qn, const double *L, double u, int *flag)
     for (int k = 0; k + 1 < qn; ++k)
         if (fabs(u - F[k] / F[qn - 1]) < ORC_FLAG_BAND) f = 1;
     *flag = f;
+    return x;
+}
+
+/* orc_categorical with its uniform given (flag bands pinned by the tests). */
+int32_t orc_categorical_draw(int32_t qn, const double *L, double u, int32_t *flag_out)
+{
+    int f = 0;
+    int x = orc_categorical(qn, L, u, &f);
+    *flag_out = f;
     return x;
 }
 
@@ -650,6 +668,16 @@ int orc_log_v(int64_t n, int64_t m, int32_t C, int32_t q_max, const int32_t *q,
     }
     orc_graph_free(&g);
     return err ? -1 : 0;
+}
+
+/* Caps the threads of the OpenMP loops (timing on one core). */
+void orc_set_threads(int32_t k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
 }
 
 /* Threads the OpenMP loops over chains use (1 without OpenMP). */

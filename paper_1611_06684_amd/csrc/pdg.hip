@@ -82,6 +82,7 @@ struct pdg_ctx {
     int64_t hub_cap = 0;         // u32 capacity of d_hub
     double *d_part = nullptr;    // [np][CB][QM - 1][64]
     int64_t part_cap = 0;        // doubles
+    bool broken = false;         // an edit failed after it began to change the store
     std::string err;
 };
 
@@ -153,6 +154,9 @@ static pdg_status scratch(pdg_ctx *ctx, int64_t bytes, void **out)
 
 static pdg_status set_dev(pdg_ctx *ctx)
 {
+    if (ctx->broken)
+        return fail(ctx, PDG_ESTATE,
+                    "an earlier edit failed while it was changing the edge store; destroy the context");
     PDG_HIP(ctx, hipSetDevice(ctx->device));
     return PDG_OK;
 }
@@ -954,7 +958,9 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     const int64_t runs = h.runs;
 
     // 3. room: move the full segments to the end of the pool, or lay every
-    //    segment out again when the pool is too small
+    //    segment out again when the pool is too small.  From here on a failure
+    //    leaves the store half changed: the context refuses every later call.
+    ctx->broken = true;
     if ((uint64_t)ctx->pool_top + h.room > (uint64_t)ctx->dev_pool_cap) {
         PDG_TRY(full_relayout(ctx, runs, uniq, runlen, ncap, noff, tmp, tb));
     } else if (h.room) {
@@ -1005,6 +1011,7 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     PDG_TRY(rebuild_hubs(ctx, hflag, hpieces, hidx, pidx, tmp, tb));
     PDG_TRY(read_sum(ctx, &h));
     ctx->hwm = h.hwm;
+    ctx->broken = false;
     return PDG_OK;
 }
 
@@ -1037,6 +1044,7 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
         return fail(ctx, PDG_ENOTFOUND,
                     "uid " + std::to_string(u) + " is not a live edge or is repeated in the batch");
     }
+    ctx->broken = true;  // as in pdg_insert_edges: a failure from here on is fatal
     k_clear_edge_records<<<grid_for(2 * m * ctx->RP), 256, 0, st>>>(m, ctx->RP, d_uid, ctx->d_ipos,
                                                                     ctx->d_rec_p);
     k_remove_apply<<<grid_for(m), 256, 0, st>>>(m, d_uid, ctx->d_src, ctx->d_dst, ctx->d_ipos,
@@ -1048,6 +1056,7 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
     ctx->ftop += m;
     ctx->live -= m;
     PDG_HIP(ctx, hipStreamSynchronize(st));
+    ctx->broken = false;
     return PDG_OK;
 }
 
@@ -1132,7 +1141,15 @@ pdg_status pdg_set_state(pdg_ctx *ctx, const uint8_t *d_x)
     if (!ctx || !d_x) return fail(ctx, PDG_EINVAL, "null argument");
     if (!ctx->nodes_set) return fail(ctx, PDG_ESTATE, "pdg_set_nodes first");
     PDG_TRY(set_dev(ctx));
-    PDG_HIP(ctx, hipMemcpyAsync(ctx->d_x, d_x, ctx->n * ctx->C, hipMemcpyDeviceToDevice, ctx->stream));
+    // every state in range before anything is copied
+    PDG_TRY(clear_flag(ctx));
+    const int64_t nc = ctx->n * ctx->C;
+    k_check_state<<<grid_for(nc), 256, 0, ctx->stream>>>(ctx->n, ctx->C, ctx->d_q, d_x, ctx->d_flag);
+    PDG_HIP(ctx, hipGetLastError());
+    uint32_t bad = 0;
+    PDG_TRY(read_flag(ctx, &bad));
+    if (bad) return fail(ctx, PDG_EINVAL, "a state x_i >= q_i");
+    PDG_HIP(ctx, hipMemcpyAsync(ctx->d_x, d_x, nc, hipMemcpyDeviceToDevice, ctx->stream));
     return PDG_OK;
 }
 
@@ -1283,9 +1300,8 @@ pdg_status pdg_get_marginals(pdg_ctx *ctx, double *d_out, int64_t *h_samples)
     if (!ctx || !d_out) return fail(ctx, PDG_EINVAL, "null argument");
     PDG_TRY(set_dev(ctx));
     const int64_t samples = ctx->counted * ctx->C;
-    const double inv = samples ? 1.0 / (double)samples : 0.0;
     const int64_t nq = ctx->n * ctx->QM;
-    k_marginals<<<grid_for(nq), 256, 0, ctx->stream>>>(nq, ctx->d_counts, inv, d_out);
+    k_marginals<<<grid_for(nq), 256, 0, ctx->stream>>>(nq, ctx->d_counts, (double)samples, d_out);
     PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (h_samples) *h_samples = samples;

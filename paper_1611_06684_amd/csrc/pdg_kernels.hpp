@@ -2008,11 +2008,19 @@ __global__ __launch_bounds__(64) void k_logv_reduce(int64_t rows, int64_t chunk,
     out[(b * CB + cb) * 64 + l] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
-__global__ void k_marginals(int64_t nq, const uint32_t *__restrict__ counts, double inv,
+// pdg_set_state's check: flag any x[i][c] >= q_i.
+__global__ void k_check_state(int64_t n, int C, const uint8_t *__restrict__ q,
+                              const uint8_t *__restrict__ x, uint32_t *__restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n * C && x[i] >= q[i / C]) *flag = 1u;
+}
+
+__global__ void k_marginals(int64_t nq, const uint32_t *__restrict__ counts, double samples,
                             double *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nq) out[i] = (double)counts[i] * inv;
+    if (i < nq) out[i] = samples > 0.0 ? (double)counts[i] / samples : 0.0;
 }
 
 }  // namespace pdg

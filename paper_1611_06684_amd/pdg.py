@@ -322,6 +322,12 @@ class Sampler:
         s = pdg_get_marginals(self.ctx, out.data_ptr())
         return out, s
 
+    def counts(self):
+        """Raw counters (int64 [n][q_max] on the host) and the samples they hold."""
+        out = self.torch.zeros((self.n, self.q_max), dtype=self.torch.int32, device=self.dev)
+        s = pdg_get_counts(self.ctx, out.data_ptr())
+        return out.cpu().numpy().view(np.uint32).astype(np.int64), s
+
     def reset_marginals(self):
         pdg_reset_marginals(self.ctx)
 

@@ -45,15 +45,27 @@ def _u64(t):
     return t.cpu().numpy().view(np.uint64)
 
 
+def _histogram(x, q_max):
+    """Per node, how many chains are in each state: int64 [n][q_max]."""
+    return np.stack([(x == a).sum(axis=1) for a in range(q_max)], axis=1).astype(np.int64)
+
+
 def teacher_forced(s, model, dec, seed, x_in, t):
-    """One sweep t on GPU and oracle from x_in.  Returns a dict of counts."""
+    """One sweep t on GPU and oracle from x_in.  Returns a dict of counts.
+    The marginal counters (counting on: t > burn-in) must grow by exactly the
+    per-node histogram of the new states, which are checked against the oracle
+    draw by draw: this covers the counting code of every primal shape."""
     import torch
     s.t = t - 1
     s.set_state(torch.as_tensor(x_in, device=s.dev))
+    cnt0, n0 = s.counts()
     s.dual_phase()
     th_g = _u64(s.duals(s.uids))
     s.primal_phase()
     x_g = s.state().cpu().numpy()
+    cnt1, n1 = s.counts()
+    assert n1 - n0 == x_in.shape[1], (n0, n1)
+    assert np.array_equal(cnt1 - cnt0, _histogram(x_g, s.q_max)), "counter delta != histogram"
     uid = _u64(s.uids)
     th_o, dflag, _, _ = oracle.sweep(model, dec, uid, seed, t, x_in)
     x_o, pflag = oracle.primal_phase(model, dec, seed, t, th_g)
@@ -109,10 +121,10 @@ def _models():
     yield "hubs_q8_f32_C8", _hub_graph(500, [8], 2, 13), 8
 
 
-def _hub_graph(n, qs, n_hubs, seed):
+def _hub_graph(n, qs, n_hubs, seed, dtype=np.float32):
     """n nodes with q uniform from qs; hub h (h < n_hubs) is joined to 300 + 130 h
     other nodes (as src or dst alternately), plus 2 n random edges; tables
-    N(0, 0.5), entries beyond a node's q zero, unaries N(0, 1), FP32."""
+    N(0, 0.5), entries beyond a node's q zero, unaries N(0, 1), FP32 (or dtype)."""
     rng = np.random.default_rng(seed)
     q = rng.choice(np.asarray(qs), size=n).astype(np.int32)
     src, dst = [], []
@@ -132,7 +144,7 @@ def _hub_graph(n, qs, n_hubs, seed):
     Lam[np.broadcast_to(ar[None, :, None] >= q[src][:, None, None], Lam.shape)] = 0.0
     Lam[np.broadcast_to(ar[None, None, :] >= q[dst][:, None, None], Lam.shape)] = 0.0
     lam[ar[None, :] >= q[:, None]] = 0.0
-    return W.Model(q, lam.astype(np.float32), src, dst, Lam.astype(np.float32), f"hubs_{n}")
+    return W.Model(q, lam.astype(dtype), src, dst, Lam.astype(dtype), f"hubs_{n}")
 
 
 @pytest.mark.parametrize("name,model,C", list(_models()), ids=[m[0] for m in _models()])
@@ -668,6 +680,15 @@ def test_error_paths():
     with pytest.raises(pdg.PdgError) as e:  # log V only between the phases
         s.log_v()
     assert e.value.code == pdg.PDG_ESTATE
+    # a state out of range (x_i = q_i, in-bounds memory) is refused, nothing copied
+    s.init()
+    x_ok = s.state().clone()
+    x_bad = x_ok.clone()
+    x_bad[17, 2] = int(model.q[17])
+    with pytest.raises(pdg.PdgError) as e:
+        s.set_state(x_bad)
+    assert e.value.code == pdg.PDG_EINVAL
+    assert torch.equal(s.state(), x_ok)
     s.dual_phase()
     with pytest.raises(pdg.PdgError) as e:
         s.insert_edges([1], [2], np.zeros((1, 3, 3), np.float32))

@@ -33,8 +33,7 @@ MUTANTS = {
     "rrow_transposed": ("rr[a] = L[a * q_max + 0] - L[0];", "rr[a] = L[0 * q_max + a] - L[0];"),
     "dual_bits_swapped": ("int y = (x_src == a), yp = (x_dst == b);",
                           "int y = (x_dst == b), yp = (x_src == a);"),
-    "dual_threshold_direction": ("if (!(u < p0)) th |= (1ull << d);",
-                                 "if (u < p0) th |= (1ull << d);"),
+    "dual_threshold_direction": ("return !(u < p0);", "return u < p0;"),
     "dual_index_stride": ("int d = (a - 1) * (qj - 1) + (b - 1);\n            if (d % 5 == 0)",
                           "int d = (a - 1) * (qi - 1) + (b - 1);\n            if (d % 5 == 0)"),
     "primal_side1_uses_beta1": ("s += pe[d * 5 + 1] + thd * pe[d * 5 + 4];",
@@ -50,6 +49,13 @@ MUTANTS = {
                       "log_cond += L[x[i * C + c]] - log(z);"),
     "logv_edge_transposed": ("log_p += Lam[(e * q_max + a) * q_max + b];",
                              "log_p += Lam[(e * q_max + b) * q_max + a];"),
+    "dual_flag_on_p_theta1": ("*flag = fabs(u - p0) < ORC_FLAG_BAND;",
+                              "*flag = fabs(u - (1.0 - p0)) < ORC_FLAG_BAND;"),
+    "flag_band_wide": ("#define ORC_FLAG_BAND 1e-6", "#define ORC_FLAG_BAND 1e-4"),
+    "cdf_flag_unnormalised": ("if (fabs(u - F[k] / F[qn - 1]) < ORC_FLAG_BAND) f = 1;",
+                              "if (fabs(u - F[k]) < ORC_FLAG_BAND) f = 1;"),
+    "cdf_flag_includes_one": ("for (int k = 0; k + 1 < qn; ++k)\n        if (fabs(u",
+                              "for (int k = 0; k < qn; ++k)\n        if (fabs(u"),
     "init_floor": ("x[i * C + c] = (uint8_t)floor(u * q[i]);",
                    "x[i * C + c] = (uint8_t)floor(u * (q[i] - 1));"),
 }
@@ -66,6 +72,10 @@ FAST_PINS = [
              for n, m in pins._tiny_models()],
     lambda: [pins.test_sampler_matches_exact_transition_rows(a, b) for a, b in ((3, 4), (4, 2))],
     lambda: [pins.test_dual_draw_frequencies_match_conditional(a, b) for a, b in ((3, 4), (4, 2))],
+    lambda: [pins.test_dual_flag_band_sits_on_p_theta0(J) for J in (0.3, 1.1)],
+    lambda: [pins.test_categorical_flag_band_sits_on_normalised_cdf(w, s)
+             for w, s in (([1.0, 2.0, 3.0, 4.0], 5.0), ([1.0, 3.0], -2.0))],
+    lambda: pins.test_flag_rate_is_the_band_width("ising"),
     pins.test_equal_weights_draw_is_floor_uq,
     pins.test_init_is_floor_uq,
     lambda: [pins.test_log_v_estimator_identities_by_enumeration(n, m)
@@ -82,8 +92,7 @@ def test_mutant_is_caught(name):
         path = os.path.join(d, "mut.c")
         so = os.path.join(d, "libmut.so")
         open(path, "w").write(src.replace(find, repl))
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-o", so, path, "-lm"])
+        subprocess.check_call(["gcc", *oracle.FLAGS, "-o", so, path, "-lm"])
         oracle.use_library(so)
         try:
             caught = []

@@ -395,3 +395,88 @@ def test_small_table_grid_marginals_vs_enumeration(shape, q, C, sweeps):
     mean, se = brute.batch_means(est)
     z = np.abs(mean - exact)[:, :q] / np.maximum(se[:, :q], 1e-12)
     assert (z < 3.5).all(), z.max()
+
+
+# ------------------------------------------------------------------ flag band
+# The parity bar excuses a GPU/oracle mismatch only for a draw whose uniform lies
+# within 1e-6 of a boundary of its conditional CDF (p(theta = 0) for a dual,
+# F_k / F_{q-1} for a node).  These pins fix where that band sits and how often
+# it fires, from values that do not come from the oracle.
+_NEAR, _FAR = 5e-7, 2e-6
+
+
+def _ising_p0(J, y, yp):
+    """p(theta = 0 | y, y') of an Ising table exp(J s s'), J >= 0, from the hand
+    derivation of the closed form: q = 2t, beta1 = beta2 = -2t with
+    t = -2 artanh(sqrt(tanh J))."""
+    t = -2.0 * np.arctanh(np.sqrt(np.tanh(J)))
+    return 1.0 / (1.0 + np.exp(2 * t - 2 * t * y - 2 * t * yp))
+
+
+@pytest.mark.parametrize("J", [0.3, 1.1])
+def test_dual_flag_band_sits_on_p_theta0(J):
+    """Uniforms placed 5e-7 from the hand-derived p(theta = 0 | y, y') are
+    flagged and decided by u < p0; at 2e-6 they are not flagged.  p0 is far
+    from 1/2 for y = y', so a band placed on p(theta = 1) fails here."""
+    m = W.ising_model(np.array([0]), np.array([1]), np.array([J]), np.zeros(2), 2)
+    par = oracle.decompose(m).par[0, 0]
+    for y in (0, 1):
+        for yp in (0, 1):
+            p0 = _ising_p0(J, y, yp)
+            for off in (-_NEAR, _NEAR):
+                th, fl = oracle.dual_decide(par, y, yp, p0 + off)
+                assert fl == 1, (y, yp, off)
+                assert th == (off > 0), (y, yp, off)
+            for off in (-_FAR, _FAR, -0.1 * p0, 0.1 * (1 - p0)):
+                th, fl = oracle.dual_decide(par, y, yp, p0 + off)
+                assert fl == 0, (y, yp, off)
+                assert th == (off > 0), (y, yp, off)
+
+
+@pytest.mark.parametrize("w,shift", [([1.0, 2.0, 3.0, 4.0], 5.0), ([1.0, 3.0], -2.0),
+                                     ([2.0, 1.0, 1.0, 4.0, 2.0], 0.0)])
+def test_categorical_flag_band_sits_on_normalised_cdf(w, shift):
+    """Logits log w + shift: the interior boundaries are the partial sums of w
+    over their total (the shift cancels).  Uniforms 5e-7 from one are flagged
+    and land on either side of it; at 2e-6 they are not; uniforms near 0 and 1
+    (no interior boundary) are never flagged."""
+    w = np.asarray(w)
+    L = np.log(w) + shift
+    F = np.cumsum(w) / w.sum()
+    for k in range(len(w) - 1):
+        for off in (-_NEAR, _NEAR):
+            x, fl = oracle.categorical_draw(L, F[k] + off)
+            assert fl == 1, (k, off)
+            assert x == (k if off < 0 else k + 1), (k, off, x)
+        for off in (-_FAR, _FAR):
+            x, fl = oracle.categorical_draw(L, F[k] + off)
+            assert fl == 0, (k, off)
+            assert x == (k if off < 0 else k + 1), (k, off, x)
+    for u in (_NEAR, 1.0 - _NEAR):
+        x, fl = oracle.categorical_draw(L, u)
+        assert fl == 0 and x == (0 if u < 0.5 else len(w) - 1)
+
+
+@pytest.mark.parametrize("kind", ["ising", "q3"])
+def test_flag_rate_is_the_band_width(kind):
+    """Over about 5e7 free-running draws the flagged count is Poisson with mean
+    2e-6 per interior boundary per draw (the band is 2e-6 wide and the uniform
+    is on a 2^-24 grid, 2e-6 * 2^24 = 33.55 points per band): one boundary per
+    dual draw, q - 1 per node draw.  Tables are moderate, so no boundary sits
+    within 1e-6 of 0 or 1 and none within 2e-6 of another.  Bounds: 5 Poisson
+    standard deviations."""
+    if kind == "ising":
+        model = W.ising_grid(60, 60, seed=81, J_half_range=0.3)
+        per_sweep = lambda: model.m + model.n  # one boundary per draw
+        C, sweeps = 8, 700
+    else:
+        model = W.table_grid(40, 40, 3, seed=82, pair_std=0.3, dtype="f64")
+        per_sweep = lambda: 4 * model.m + 2 * model.n
+        C, sweeps = 8, 500
+    dec = oracle.decompose(model)
+    x = oracle.init_state(model, C, 5)
+    uid = np.arange(1, model.m + 1, dtype=np.uint64)
+    _, nf, nd = oracle.run(model, dec, uid, 5, x, 0, sweeps, burn_in=0)
+    lam = 2e-6 * per_sweep() * C * sweeps
+    assert nd >= 2e7
+    assert abs(nf - lam) < 5 * np.sqrt(lam), (nf, lam, nd)
