@@ -1,0 +1,20 @@
+"""Mixing of the sampler on the GPU by the PSRF of Sec. 6 (``-m gpu``): on a 50 x
+50 Ising grid without field and 10 chains, the grid's PSRF falls below 1.01 and
+stays there for weak couplings, and it takes longer as the coupling grows."""
+from __future__ import annotations
+
+import pytest
+
+from paper_1611_06684_amd import mixing
+
+pytestmark = pytest.mark.gpu
+
+
+def test_psrf_mixing_time_grows_with_coupling():
+    times = []
+    for beta in (0.1, 0.3):
+        pts, vals, mt = mixing.psrf_trace(beta, max_sweeps=3000)
+        print(f"beta {beta}: mixing time {mt} sweeps, final PSRF {vals[-1]:.4f}", flush=True)
+        assert mt is not None, (beta, vals[-8:])
+        times.append(mt)
+    assert times[0] < times[1]
