@@ -166,6 +166,19 @@ pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_
  * context's stream; d_out is written when that work completes. */
 pdg_status pdg_log_v(pdg_ctx *ctx, double *d_out);
 
+/* pdg_log_v for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result, bit for bit, with the partial sums in a static
+ * workspace of 64 MiB that the library holds on every device it runs on (for
+ * the process's lifetime) instead of the context's growable scratch.  Calls no
+ * hipMalloc, hipFree or allocating library routine.  Needs (ceil(n/16) +
+ * ceil(edge slots/64) + min(that, 1024) + 1) * 64 * ceil(C/64) * 8 bytes
+ * (ceil(C/64) read as 1 for C <= 32); larger graphs get PDG_ECAPACITY and
+ * nothing is launched.  Every context on a device shares that device's
+ * workspace: calls on one device that overlap in time (other streams, other
+ * host threads) race and must be ordered by the caller. */
+pdg_status pdg_log_v_noalloc(pdg_ctx *ctx, double *d_out);
+
 /* Marginal estimates p(x_i = a) = count / samples into d_out: double
  * [n][q_max], one correctly rounded FP64 division per entry (0 before any
  * counted sweep; entries a >= q_i are 0); *h_samples (optional) = C x counted

@@ -14,6 +14,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -83,8 +84,18 @@ struct pdg_ctx {
     double *d_part = nullptr;    // [np][CB][QM - 1][64]
     int64_t part_cap = 0;        // doubles
     bool broken = false;         // an edit failed after it began to change the store
+    void *d_static = nullptr;    // this device's copy of the static workspace (pdg_log_v_noalloc)
     std::string err;
 };
+
+// Static workspace of pdg_log_v_noalloc (callers that cannot allocate): every
+// device the library runs on holds its own copy until the process ends.  Host
+// code never uses the name itself; each context keeps this device's address of
+// it, taken once per device when the first context is created there.
+constexpr int64_t kStaticScratchBytes = 64ll << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / 8];
+static std::mutex g_static_mu;
+static void *g_static_addr[256];
 
 namespace pdg {
 
@@ -138,7 +149,7 @@ static pdg_status dalloc(pdg_ctx *ctx, void **p, int64_t bytes)
     return PDG_OK;
 }
 
-static pdg_status scratch(pdg_ctx *ctx, int64_t bytes, void **out)
+static pdg_status ctx_scratch(pdg_ctx *ctx, int64_t bytes, void **out)
 {
     if (bytes > ctx->scratch_bytes) {
         if (ctx->d_scratch) PDG_HIP(ctx, hipFree(ctx->d_scratch));
@@ -789,6 +800,17 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
         return code;
     };
     if (hipSetDevice(device) != hipSuccess) return bail(fail(ctx, PDG_EHIP, "hipSetDevice failed"));
+    if (device >= 256) return bail(fail(ctx, PDG_EINVAL, "device index above 255"));
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (!g_static_addr[device]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+                return bail(fail(ctx, PDG_EHIP, "hipGetSymbolAddress of the static workspace failed"));
+            g_static_addr[device] = p;
+        }
+        ctx->d_static = g_static_addr[device];
+    }
     const int64_t N = cfg->node_capacity, S = cfg->edge_capacity;
     const int64_t N4 = (N + 3) / 4 * 4;  // segment tables are read per node quad
     // slot arrays are read in groups of kDualEdgesPerWave slots
@@ -911,7 +933,7 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
                           3 * Carve::size<int32_t>(m) + 4 * Carve::size<uint32_t>(n) +
                           a256((int64_t)tb);
     void *sp;
-    PDG_TRY(scratch(ctx, bytes, &sp));
+    PDG_TRY(ctx_scratch(ctx, bytes, &sp));
     Carve cv{static_cast<char *>(sp)};
     uint32_t *keys = cv.take<uint32_t>(m2), *vals = cv.take<uint32_t>(m2);
     uint32_t *keys2 = cv.take<uint32_t>(m2), *vals2 = cv.take<uint32_t>(m2);
@@ -1027,7 +1049,7 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
     const hipStream_t st = ctx->stream;
     EditSummary *sum = ctx->d_sum;
     void *sp;
-    PDG_TRY(scratch(ctx, Carve::size<uint32_t>(2 * m), &sp));
+    PDG_TRY(ctx_scratch(ctx, Carve::size<uint32_t>(2 * m), &sp));
     uint32_t *list = static_cast<uint32_t *>(sp);
 
     // every uid live and named once, else nothing changes
@@ -1076,7 +1098,7 @@ pdg_status pdg_live_uids(pdg_ctx *ctx, uint64_t *d_uid_out)
     PDG_HIP(ctx, hipcub::DeviceSelect::If(nullptr, tb, ctx->d_uid, d_uid_out, &ctx->d_sum->sel,
                                           (int)ctx->hwm, NonZeroU64(), ctx->stream));
     void *sp;
-    PDG_TRY(scratch(ctx, (int64_t)tb + 256, &sp));
+    PDG_TRY(ctx_scratch(ctx, (int64_t)tb + 256, &sp));
     PDG_HIP(ctx, hipcub::DeviceSelect::If(sp, tb, ctx->d_uid, d_uid_out, &ctx->d_sum->sel,
                                           (int)ctx->hwm, NonZeroU64(), ctx->stream));
     PDG_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -1248,7 +1270,7 @@ pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_
     if (!d_uid || !d_theta_out) return fail(ctx, PDG_EINVAL, "null pointer");
     PDG_TRY(set_dev(ctx));
     void *sp;
-    PDG_TRY(scratch(ctx, 4 * m + 64, &sp));
+    PDG_TRY(ctx_scratch(ctx, 4 * m + 64, &sp));
     int32_t *slots = static_cast<int32_t *>(sp);
     PDG_TRY(reset_sum(ctx));
     k_uid_slots<<<grid_for(m), 256, 0, ctx->stream>>>(m, d_uid, ctx->S, ctx->d_uid, slots,
@@ -1263,18 +1285,27 @@ pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_
     return PDG_OK;
 }
 
-pdg_status pdg_log_v(pdg_ctx *ctx, double *d_out)
+namespace pdg {
+
+// Bytes of workspace one log V call needs: a row of per-chain partial sums per
+// node block and edge block, the reduction's middle rows and the final row.
+static int64_t log_v_bytes(const pdg_ctx *ctx, int64_t *bn, int64_t *be, int64_t *nb)
 {
-    if (!ctx || !d_out) return fail(ctx, PDG_EINVAL, "null argument");
-    if (ctx->phase != 1) return fail(ctx, PDG_ESTATE, "log V is taken between the two phases");
-    PDG_TRY(set_dev(ctx));
+    *bn = cdiv(ctx->n, 16);
+    *be = cdiv(ctx->hwm, 4 * kLvEdges);
+    const int64_t rows = *bn + *be, row = (int64_t)ctx->CB * 64;
+    *nb = std::min<int64_t>(rows, 1024);
+    return (rows + *nb + 1) * row * 8;
+}
+
+// log V into d_out with the workspace `ws` (at least log_v_bytes): node and edge
+// kernels write every row, the two reductions read only rows written before.
+static pdg_status log_v_into(pdg_ctx *ctx, double *d_out, double *ws, int64_t bn, int64_t be,
+                             int64_t nb)
+{
     const Graph g = make_graph(ctx);
-    const int64_t bn = cdiv(ctx->n, 16), be = cdiv(ctx->hwm, 4 * kLvEdges);
-    const int64_t rows = bn + be, row = (int64_t)g.CB * 64;
-    const int64_t nb = std::min<int64_t>(rows, 1024), chunk = cdiv(rows, nb);
-    void *sp;
-    PDG_TRY(scratch(ctx, (rows + nb + 1) * row * 8 + 256, &sp));
-    double *pn = static_cast<double *>(sp), *pe = pn + bn * row, *mid = pn + rows * row;
+    const int64_t rows = bn + be, row = (int64_t)g.CB * 64, chunk = cdiv(rows, nb);
+    double *pn = ws, *pe = pn + bn * row, *mid = pn + rows * row;
     switch (ctx->QM) {
     case 2: logv_q<2>(ctx, g, bn, be, pn, pe); break;
     case 3: logv_q<3>(ctx, g, bn, be, pn, pe); break;
@@ -1290,9 +1321,39 @@ pdg_status pdg_log_v(pdg_ctx *ctx, double *d_out)
                                                                               pn, mid);
     double *fin = mid + nb * row;
     k_logv_reduce<<<dim3(1, (unsigned)g.CB), 64, 0, ctx->stream>>>(nb, nb, g.CB, mid, fin);
+    PDG_HIP(ctx, hipGetLastError());
     PDG_HIP(ctx, hipMemcpyAsync(d_out, fin, (size_t)ctx->C * 8, hipMemcpyDeviceToDevice,
                                 ctx->stream));
     return PDG_OK;
+}
+
+}  // namespace pdg
+
+pdg_status pdg_log_v(pdg_ctx *ctx, double *d_out)
+{
+    if (!ctx || !d_out) return fail(ctx, PDG_EINVAL, "null argument");
+    if (ctx->phase != 1) return fail(ctx, PDG_ESTATE, "log V is taken between the two phases");
+    PDG_TRY(set_dev(ctx));
+    int64_t bn, be, nb;
+    const int64_t bytes = log_v_bytes(ctx, &bn, &be, &nb);
+    void *sp;
+    PDG_TRY(ctx_scratch(ctx, bytes + 256, &sp));
+    return log_v_into(ctx, d_out, static_cast<double *>(sp), bn, be, nb);
+}
+
+pdg_status pdg_log_v_noalloc(pdg_ctx *ctx, double *d_out)
+{
+    if (!ctx || !d_out) return fail(ctx, PDG_EINVAL, "null argument");
+    if (ctx->phase != 1) return fail(ctx, PDG_ESTATE, "log V is taken between the two phases");
+    PDG_TRY(set_dev(ctx));
+    int64_t bn, be, nb;
+    const int64_t bytes = log_v_bytes(ctx, &bn, &be, &nb);
+    if (bytes > kStaticScratchBytes)
+        return fail(ctx, PDG_ECAPACITY,
+                    "log V of this graph needs " + std::to_string(bytes) +
+                        " bytes of workspace; the static workspace holds " +
+                        std::to_string(kStaticScratchBytes));
+    return log_v_into(ctx, d_out, static_cast<double *>(ctx->d_static), bn, be, nb);
 }
 
 pdg_status pdg_get_marginals(pdg_ctx *ctx, double *d_out, int64_t *h_samples)

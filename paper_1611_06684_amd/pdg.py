@@ -28,6 +28,7 @@ EXPORTS = [
     "pdg_set_state", "pdg_get_state", "pdg_get_sweep", "pdg_set_sweep", "pdg_sweep",
     "pdg_dual_phase", "pdg_primal_phase", "pdg_get_duals", "pdg_get_marginals",
     "pdg_get_counts", "pdg_reset_marginals", "pdg_sync", "pdg_last_error", "pdg_log_v",
+    "pdg_log_v_noalloc",
 ]
 
 
@@ -79,6 +80,7 @@ def lib():
             "pdg_primal_phase": ([_P], S),
             "pdg_get_duals": ([_P, _I64, _P, _P], S),
             "pdg_log_v": ([_P, _P], S),
+            "pdg_log_v_noalloc": ([_P, _P], S),
             "pdg_get_marginals": ([_P, _P, ctypes.POINTER(_I64)], S),
             "pdg_get_counts": ([_P, _P, ctypes.POINTER(_I64)], S),
             "pdg_reset_marginals": ([_P], S),
@@ -186,6 +188,10 @@ def pdg_get_duals(ctx, m, d_uid, d_theta_out):
 
 def pdg_log_v(ctx, d_out):
     _chk(lib().pdg_log_v(ctx, d_out), ctx)
+
+
+def pdg_log_v_noalloc(ctx, d_out):
+    _chk(lib().pdg_log_v_noalloc(ctx, d_out), ctx)
 
 
 def pdg_get_marginals(ctx, d_out) -> int:
