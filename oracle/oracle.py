@@ -110,6 +110,8 @@ def _declare(L):
     L.orc_primal_phase.restype = ctypes.c_int
     L.orc_num_threads.argtypes = []
     L.orc_num_threads.restype = ctypes.c_int
+    L.orc_uniform_batch.argtypes = [_U64, _U32, _U32, _I64, _P, _P, _P, _P]
+    L.orc_uniform_batch.restype = None
     L.orc_set_threads.argtypes = [_I32]
     L.orc_set_threads.restype = None
     L.orc_all_logits.argtypes = [_I64, _I64, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]
@@ -139,6 +141,18 @@ def philox4x32_10(ctr, key) -> np.ndarray:
 
 def uniform(seed, phase, ident, sub, sweep, slot) -> float:
     return lib().orc_uniform(seed, phase, ident, sub, sweep, slot)
+
+
+def uniforms(seed, phase, sweep, ids, subs, slots) -> np.ndarray:
+    """Vector form of uniform(): arrays ids (u64), subs (u32), slots (0..4)."""
+    shape = np.broadcast(np.asarray(ids), np.asarray(subs), np.asarray(slots)).shape
+    ids, pi = _c(np.broadcast_to(np.asarray(ids, np.uint64), shape).ravel(), np.uint64)
+    subs, ps = _c(np.broadcast_to(subs, shape).ravel(), np.uint32)
+    slots, pl = _c(np.broadcast_to(slots, shape).ravel(), np.int32)
+    out = np.zeros(shape, np.float64)
+    lib().orc_uniform_batch(int(seed), int(phase), int(sweep), out.size, pi, ps, pl,
+                            out.ctypes.data_as(_P))
+    return out
 
 
 # ----------------------------------------------------------------- decomposition

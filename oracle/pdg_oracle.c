@@ -112,6 +112,16 @@ double orc_uniform(uint64_t seed, uint32_t phase, uint64_t id, uint32_t sub,
     return orc_u24_to_unit(orc_u24(w, slot));
 }
 
+/* Many uniforms of one phase and sweep: out[k] = orc_uniform(seed, phase,
+ * ids[k], subs[k], sweep, slots[k]). */
+void orc_uniform_batch(uint64_t seed, uint32_t phase, uint32_t sweep, int64_t n,
+                       const uint64_t *ids, const uint32_t *subs, const int32_t *slots,
+                       double *out)
+{
+    for (int64_t k = 0; k < n; ++k)
+        out[k] = orc_uniform(seed, phase, ids[k], subs[k], sweep, slots[k]);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Sec. 4.1: factorization of a strictly positive 2x2 table.                  */
 /* P, B, C row-major: P[0]=p11, P[1]=p12, P[2]=p21, P[3]=p22.                 */
