@@ -177,13 +177,16 @@ def proposal_logprob(xb, logits):
     return (xb * logits - np.logaddexp(0.0, logits)).sum(-1)
 
 
-def mh_step(blk: Blocking, x, f, K, logits, seed, s):
-    """Proposal draws and acceptance for every block and chain: returns (x_new,
-    accepted [nb][C], flag [nb][C]).  logits [nb][C][bs^2] (FP32 values)."""
+def mh_step(blk: Blocking, x, f, K, logits, seed, s, blocks=None):
+    """Proposal draws and acceptance for every block (or the listed blocks,
+    whose rows f, K, logits then hold in that order) and chain: returns (x_new,
+    accepted [nb][C], flag [nb][C], proposals [nb][C][bs^2]).  logits (FP32
+    values) [nb][C][bs^2]."""
     x_new = x.copy()
     nb, C, k = f.shape
+    ids = np.arange(nb) if blocks is None else np.asarray(blocks)
     calls = (k + 1 + 4) // 5
-    b_ids = np.arange(nb, dtype=np.uint64)[:, None, None]
+    b_ids = ids.astype(np.uint64)[:, None, None]
     c_ids = np.arange(C, dtype=np.uint32)[None, :, None]
     d = np.arange(k + 1)[None, None, :]
     u = O.uniforms(seed, PHASE_BLOCK, s, np.broadcast_to(b_ids, (nb, C, k + 1)),
@@ -194,7 +197,7 @@ def mh_step(blk: Blocking, x, f, K, logits, seed, s):
     p1 = 1.0 / (1.0 + np.exp(-lg))
     xp = (u[..., :k] < p1).astype(np.uint8)
     flag = (np.abs(u[..., :k] - p1) < BAND_MH).any(-1)
-    xb = np.transpose(x[blk.nodes], (0, 2, 1))  # [nb][C][k]
+    xb = np.transpose(x[blk.nodes[ids]], (0, 2, 1))  # [nb][C][k]
     accepted = np.zeros((nb, C), bool)
     for b in range(nb):
         la = mh_log_accept(xb[b], xp[b], f[b], K[b], lg[b])
@@ -202,8 +205,8 @@ def mh_step(blk: Blocking, x, f, K, logits, seed, s):
         accepted[b] = lu < la
         flag[b] |= np.abs(lu - la) < BAND_MH
         for c in np.flatnonzero(accepted[b]):
-            x_new[blk.nodes[b], c] = xp[b, c]
-    return x_new, accepted, flag
+            x_new[blk.nodes[ids[b]], c] = xp[b, c]
+    return x_new, accepted, flag, xp
 
 
 # ------------------------------------------------------------------ network

@@ -21,6 +21,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "pdg.h"
+#include "pdg_view.hpp"
 #include "pdg_kernels.hpp"
 #include "pdg_store.hpp"
 
@@ -171,6 +172,23 @@ static pdg_status set_dev(pdg_ctx *ctx)
     PDG_HIP(ctx, hipSetDevice(ctx->device));
     return PDG_OK;
 }
+
+pdg_status report(pdg_ctx *ctx, pdg_status code, const std::string &msg)
+{
+    return fail(ctx, code, msg);
+}
+
+pdg_status ctx_view(pdg_ctx *ctx, CtxView *v)
+{
+    if (!ctx) return fail(nullptr, PDG_EINVAL, "null context");
+    if (!ctx->nodes_set) return fail(ctx, PDG_ESTATE, "pdg_set_nodes first");
+    PDG_TRY(set_dev(ctx));
+    *v = CtxView{ctx->device, ctx->stream, ctx->d_x,          ctx->d_q,
+                 ctx->n,      ctx->C,      ctx->QM,           ctx->cfg.precision,
+                 ctx->cfg.seed, ctx->phase};
+    return PDG_OK;
+}
+
 
 static pdg_status read_flag(pdg_ctx *ctx, uint32_t *h)
 {

@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1611_06684_amd import pdg
@@ -13,8 +14,8 @@ from paper_1611_06684_amd import pdg
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    txt = open(os.path.join(ROOT, "include", "pdg.h")).read()
+def _declared(header="pdg.h"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     return sorted(set(re.findall(r"^(?:pdg_status|const char \*)\s*(pdg_\w+)\(", txt, re.M)))
 
 
@@ -22,12 +23,27 @@ def test_header_and_binding_agree():
     declared = _declared()
     assert len(declared) >= 20
     assert sorted(pdg.EXPORTS) == declared
+    from paper_1611_06684_amd import pdg_block
+    assert sorted(pdg_block.EXPORTS) == _declared("pdg_block.h")
 
 
 def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(pdg.LIB_PATH)
-    for name in _declared():
+    for name in _declared() + _declared("pdg_block.h"):
         assert hasattr(L, name), name
+
+
+def test_packed_network_layout_matches_header():
+    from paper_1611_06684_amd import pdg_block as pb
+    txt = open(os.path.join(ROOT, "include", "pdg_block.h")).read()
+    for name, off in pb.OFF.items():
+        key = "PDG_MLP_OFF_" + name.upper()
+        assert re.search(key + r" = (\d+)", txt).group(1) == str(off)
+    total = 0
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert pb.OFF[name] == total
+        total += int(np.prod(pb.SHAPE[name]))
+    assert total == pb.MLP_PARAMS
 
 
 def test_params_layout():

@@ -138,7 +138,7 @@ def test_exact_proposal_is_always_accepted():
     th, _ = B.cut_duals(model, dec, blk, x, 3, 1)
     fb, internal = B.block_fields(model, dec, blk, th)
     Kb = B.block_couplings(blk, internal)
-    _, acc, _ = B.mh_step(blk, x, fb, Kb, fb.copy(), 3, 1)
+    _, acc, _, _ = B.mh_step(blk, x, fb, Kb, fb.copy(), 3, 1)
     assert acc.all()
 
 
@@ -162,7 +162,7 @@ def test_sampled_transitions_match_the_mh_matrix():
     fC = np.repeat(f, C, axis=1)
     lC = np.broadcast_to(logits, (1, C, 4)).astype(np.float32).astype(np.float64)
     for s in range(1, steps + 1):
-        xn, _, _ = B.mh_step(blk, x, fC, K, lC, 11, s)
+        xn, _, _, _ = B.mh_step(blk, x, fC, K, lC, 11, s)
         idx = (xn.T[:, None, :] == S[None]).all(-1).argmax(-1)
         counts += np.bincount(idx, minlength=16)
     _, T32 = _mh_matrix(f[0, 0], K[0], lC[0, 0])
