@@ -129,8 +129,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=None)
-    p.add_argument("--workload", choices=["dynamic-sparse", "plain-grid", "tiny", "batched"],
+    p.add_argument("--workload", choices=["dynamic-sparse", "plain-grid", "tiny", "batched",
+                                          "learned"],
                    default="dynamic-sparse")
+    p.add_argument("--epochs", type=int, default=2, help="learned workload: training epochs")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--batch-layout", choices=["by-states", "one"], default="by-states",
                    help="batched workload: one context per state count (records sized for "
@@ -529,6 +531,88 @@ def run_batched(args):
     return out
 
 
+MLP_FLOP_PER_ROW = 2 * (96 * 256 + 256 * 256 + 256 * 64)
+BF16_PEAK = 2.5e15
+
+
+def run_learned(args):
+    """Learned block proposal on the 512 x 512 grid (128 chains): ESS/s of
+    learned step + plain sweep against plain sweeps, at equal marginal error."""
+    import torch
+    from paper_1611_06684_amd import learned as L
+    from paper_1611_06684_amd import pdg_block as pb
+    from paper_1611_06684_amd.pdg import Sampler
+    iters = 2000 if args.steps is None else args.steps
+    warmup = 500 if args.warmup is None else args.warmup
+    side, C, seed = 512, 128, 0
+    model = L.grid_model(side, seed=0)
+    log("reference marginals (independent plain chains)")
+    p_ref = L.reference_marginals(model, C, 100, 500, 4000)
+    s = Sampler(model, C, seed=seed, burn_in=0)
+    s.init()
+    s.sweep(warmup)
+    bp = pb.BlockProposal(s, model, side, side, init_seed=0)
+    log("collecting training rows")
+    X, T = L.collect_training_rows(s, bp, snapshots=2, gap=50)
+    n_rows = X.shape[0]
+    losses, train_s = L.train(bp, X, T, epochs=args.epochs, log=log)
+    del X, T
+    # the network alone: one forward over every block and chain
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        pb.pdg_mlp_forward(bp.wbf.data_ptr(), bp.w32.data_ptr(), bp.rows, bp.x_in.data_ptr(),
+                           bp.logits.data_ptr(), stream=bp.stream)
+    a.record(st)
+    for _ in range(20):
+        pb.pdg_mlp_forward(bp.wbf.data_ptr(), bp.w32.data_ptr(), bp.rows, bp.x_in.data_ptr(),
+                           bp.logits.data_ptr(), stream=bp.stream)
+    b.record(st)
+    b.synchronize()
+    mlp_ms = a.elapsed_time(b) / 20
+    ms_plain = L.time_iterations(s, None, 200)
+    ms_learned = L.time_iterations(s, bp, 200)
+    rng = np.random.default_rng(1)
+    nodes = np.sort(rng.choice(model.n, size=256, replace=False))
+    log("ESS runs")
+    ess_p, mp = L.ess_run(s, None, iters, nodes)
+    _, _, acc0, prop0 = pb.pdg_blk_info(bp.blk, s.ctx)
+    ess_l, ml = L.ess_run(s, bp, iters, nodes)
+    _, _, acc1, prop1 = pb.pdg_blk_info(bp.blk, s.ctx)
+    bp.close()
+    s.close()
+    med_p, med_l = float(np.median(ess_p)), float(np.median(ess_l))
+    esss_p = med_p / (iters * ms_plain / 1e3)
+    esss_l = med_l / (iters * ms_learned / 1e3)
+    err_p = float(np.abs(mp - p_ref).mean())
+    err_l = float(np.abs(ml - p_ref).mean())
+    flops = bp.rows * MLP_FLOP_PER_ROW
+    achieved = flops / (mlp_ms / 1e3)
+    return {
+        "metric": "ESS/s of the learned block proposal (median over nodes) at marginal error <= 0.01",
+        "value": esss_l, "unit": "effective samples/s",
+        "n_gpus": 1, "steps": iters, "warmup": warmup,
+        "ms_per_step": ms_learned, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 network, f64 MH", "data": "synthetic",
+        "config": {"workload": f"learned proposal: {side}x{side} binary grid, J~U(0,0.35), "
+                               f"h~N(0,0.3), 8x8 blocks, {C} chains",
+                   "plain_ess_per_s": esss_p, "ratio_learned_over_plain": esss_l / esss_p,
+                   "ess_median": {"plain": med_p, "learned": med_l},
+                   "ess_p10": {"plain": float(np.percentile(ess_p, 10)),
+                               "learned": float(np.percentile(ess_l, 10))},
+                   "ms_per_iteration": {"plain": ms_plain, "learned": ms_learned},
+                   "marginal_error": {"plain": err_p, "learned": err_l},
+                   "acceptance": (acc1 - acc0) / max(prop1 - prop0, 1),
+                   "training": {"rows": n_rows, "epochs": args.epochs, "loss_per_epoch": losses,
+                                "wall_s": train_s},
+                   "tracked_nodes": len(nodes)},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK, "unit": "FLOP/s",
+                     "frac": achieved / BF16_PEAK, "traffic": None,
+                     "kernel": "k_mlp_fwd (proposal network, BF16 MFMA)",
+                     "units_per_launch": flops, "launch_ms": mlp_ms},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -537,7 +621,7 @@ def main():
               "multi-GPU path is implemented.", file=sys.stderr)
         sys.exit(2)
     run = {"plain-grid": run_plain, "dynamic-sparse": run_dynamic, "tiny": run_tiny,
-           "batched": run_batched}
+           "batched": run_batched, "learned": run_learned}
     out = run[args.workload](args)
     print(json.dumps(out), flush=True)
     if args.copy_mib > 0:

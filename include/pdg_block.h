@@ -87,8 +87,9 @@ pdg_status pdg_blk_inputs(pdg_blk *b, uint16_t *d_in, uint8_t *d_target, double 
  * logits d_logits float [nb C][64]; accepted proposals are written to the
  * context's x.  Optional outputs per row: d_prop uint8 [nb C][64] the proposal,
  * d_acc uint8 [nb C] 1 if accepted, d_flag uint8 [nb C] 1 if a proposal
- * uniform lies within 1e-9 of its sigmoid(l) or log u within 1e-9 of the log
- * acceptance ratio (FP64; the decision there depends on rounding). */
+ * uniform lies within 1e-6 of its sigmoid(l) (evaluated in FP32) or log u
+ * within 1e-9 of the log acceptance ratio (FP64): there the decision depends
+ * on rounding. */
 pdg_status pdg_blk_mh(pdg_blk *b, const float *d_logits, uint8_t *d_prop, uint8_t *d_acc,
                       uint8_t *d_flag);
 /* Cut duals of the last pdg_blk_cut_duals: uint8 [m][C] in grid edge order

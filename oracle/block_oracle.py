@@ -36,8 +36,9 @@ draws with id 2^63 + e, sub 16 c, slot 0; block b draws its 65 uniforms with
 id b, sub 16 c + floor(d / 5), slot d mod 5 (d < 64: the proposal bit of block
 node d, row-major in the block; d = 64: the acceptance), all at counter s.
 Flags: a draw whose uniform is within 1e-6 of p(theta = 0) (cut duals, as in
-the dual phase) or within 1e-9 of sigmoid(l) (proposal), or whose log u is
-within 1e-9 of log a (acceptance).
+the dual phase) or of sigmoid(l) (proposal bits: the GPU evaluates the sigmoid
+in FP32), or whose log u is within 1e-9 of log a (acceptance, FP64 on both
+sides).
 
 The proposal network (an MLP, BF16 weights, FP32 accumulation on the GPU) is
 evaluated here in FP64 on the same BF16 values, with every activation rounded
@@ -52,6 +53,7 @@ from . import oracle as O
 PHASE_BLOCK = 3
 CUT_ID = np.uint64(1) << np.uint64(63)
 BAND_DUAL = 1e-6
+BAND_PROP = 1e-6
 BAND_MH = 1e-9
 
 
@@ -196,7 +198,7 @@ def mh_step(blk: Blocking, x, f, K, logits, seed, s, blocks=None):
     lg = np.asarray(logits, np.float64)
     p1 = 1.0 / (1.0 + np.exp(-lg))
     xp = (u[..., :k] < p1).astype(np.uint8)
-    flag = (np.abs(u[..., :k] - p1) < BAND_MH).any(-1)
+    flag = (np.abs(u[..., :k] - p1) < BAND_PROP).any(-1)
     xb = np.transpose(x[blk.nodes[ids]], (0, 2, 1))  # [nb][C][k]
     accepted = np.zeros((nb, C), bool)
     for b in range(nb):

@@ -158,100 +158,175 @@ struct BlockGeo {
     const uint8_t *theta;
 };
 
-// f of block node p for chain c: f0 plus the fields of its cut edges given
-// their duals (top, bottom, left, right; the node is dst of a top / left cut
-// edge and src of a bottom / right one).
-__device__ __forceinline__ double block_field(const BlockGeo &g, int64_t b, int c, int p, int64_t node)
-{
-    const int row = p >> 3, col = p & 7;
-    double f = g.f0[node];
-    auto add = [&](int t, bool src) {
-        const int k = g.slot[b * 32 + t];
-        if (k >= 0) {
-            const double th = (double)g.theta[(int64_t)k * g.C + c];
-            f += src ? g.fld[4 * k + 0] + th * g.fld[4 * k + 2] : g.fld[4 * k + 1] + th * g.fld[4 * k + 3];
-        }
-    };
-    if (row == 0) add(col, false);
-    if (row == 7) add(8 + col, true);
-    if (col == 0) add(16 + row, false);
-    if (col == 7) add(24 + row, true);
-    return f;
-}
-
 __device__ __forceinline__ int64_t block_node(const BlockGeo &g, int64_t b, int p)
 {
     const int64_t R0 = (b / g.nbc) * BS, C0 = (b % g.nbc) * BS;
     return (R0 + (p >> 3)) * g.W + C0 + (p & 7);
 }
 
-// Network inputs: wave per (block, chain), lane = block node.
-__global__ __launch_bounds__(256) void k_inputs(BlockGeo g, int64_t nb, const uint8_t *__restrict__ x,
+// The block kernels take one block and a tile of up to CT chains per
+// work-group: the block's states and cut duals for the tile are staged in LDS
+// (each node's chains are contiguous bytes in x, so the loads coalesce), then
+// each wave takes the tile's chains in turn with lane = block node.
+constexpr int CT = 64;
+
+struct LaneSlots {
+    // up to two cut edges of a block node (top / bottom, then left / right):
+    // slot index, constant field, field per unit dual
+    int t[2];
+    double c0[2], hc[2];
+};
+
+__device__ __forceinline__ LaneSlots lane_slots(const BlockGeo &g, int64_t b, int p)
+{
+    LaneSlots s;
+    const int row = p >> 3, col = p & 7;
+    int n = 0;
+    s.t[0] = s.t[1] = -1;
+    s.c0[0] = s.c0[1] = s.hc[0] = s.hc[1] = 0.0;
+    auto take = [&](int t, bool src) {
+        const int k = g.slot[b * 32 + t];
+        if (k >= 0) {
+            s.t[n] = t;
+            s.c0[n] = src ? g.fld[4 * k + 0] : g.fld[4 * k + 1];
+            s.hc[n] = src ? g.fld[4 * k + 2] : g.fld[4 * k + 3];
+            ++n;
+        }
+    };
+    if (row == 0) take(col, false);
+    if (row == 7) take(8 + col, true);
+    if (col == 0) take(16 + row, false);
+    if (col == 7) take(24 + row, true);
+    return s;
+}
+
+// f of the lane's node for tile chain c: f0 plus its cut edges' fields in the
+// order top, bottom, left, right.
+__device__ __forceinline__ double tile_field(double f0, const LaneSlots &s, const uint8_t (*ts)[CT], int c)
+{
+    double f = f0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        if (s.t[j] >= 0) f += s.c0[j] + (double)ts[s.t[j]][c] * s.hc[j];
+    return f;
+}
+
+__device__ __forceinline__ void stage_tile(const BlockGeo &g, int64_t b, int c0, int nc,
+                                           const uint8_t *__restrict__ x, uint8_t (*xs)[CT],
+                                           uint8_t (*ts)[CT])
+{
+    for (int q = threadIdx.x; q < 64 * CT; q += 256) {
+        const int p = q / CT, c = q - p * CT;
+        xs[p][c] = c < nc ? x[block_node(g, b, p) * g.C + c0 + c] : (uint8_t)0;
+    }
+    for (int q = threadIdx.x; q < 32 * CT; q += 256) {
+        const int t = q / CT, c = q - t * CT;
+        const int k = g.slot[b * 32 + t];
+        ts[t][c] = (c < nc && k >= 0) ? g.theta[(int64_t)k * g.C + c0 + c] : (uint8_t)0;
+    }
+}
+
+// Network inputs, targets and fields: grid (blocks, chain tiles).
+__global__ __launch_bounds__(256) void k_inputs(BlockGeo g, const uint8_t *__restrict__ x,
                                                 uint16_t *__restrict__ in, uint8_t *__restrict__ tgt,
                                                 double *__restrict__ fout)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= nb * g.C) return;
-    const int64_t b = w / g.C;
-    const int c = (int)(w - b * g.C);
+    __shared__ uint8_t xs[64][CT];
+    __shared__ uint8_t ts[32][CT];
+    const int64_t b = blockIdx.x;
+    const int c0 = blockIdx.y * CT, nc = min(CT, g.C - c0);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    stage_tile(g, b, c0, nc, x, xs, ts);
+    __syncthreads();
     const int64_t node = block_node(g, b, lane);
-    const double f = block_field(g, b, c, lane, node);
-    in[w * NIN + lane] = bf16_bits((float)f);
-    if (lane < 32) {
-        const int k = g.slot[b * 32 + lane];
-        in[w * NIN + 64 + lane] = (k >= 0 && g.theta[(int64_t)k * g.C + c]) ? (uint16_t)0x3F80u : (uint16_t)0u;
+    const double f0 = g.f0[node];
+    const LaneSlots sl = lane_slots(g, b, lane);
+    for (int c = wv; c < nc; c += 4) {
+        const int64_t row = b * g.C + c0 + c;
+        const double f = tile_field(f0, sl, ts, c);
+        in[row * NIN + lane] = bf16_bits((float)f);
+        if (lane < 32) in[row * NIN + 64 + lane] = ts[lane][c] ? (uint16_t)0x3F80u : (uint16_t)0u;
+        if (tgt) tgt[row * 64 + lane] = xs[lane][c];
+        if (fout) fout[row * 64 + lane] = f;
     }
-    if (tgt) tgt[w * 64 + lane] = x[node * g.C + c];
-    if (fout) fout[w * 64 + lane] = f;
 }
 
-// Metropolis-Hastings move: wave per (block, chain), lane = block node.
-__global__ __launch_bounds__(256) void k_mh(BlockGeo g, int64_t nb, uint8_t *__restrict__ x,
+// Metropolis-Hastings move: grid (blocks, chain tiles); accepted proposals go
+// into the staged tile, which is written back whole.
+__global__ __launch_bounds__(256) void k_mh(BlockGeo g, uint8_t *__restrict__ x,
                                             const float *__restrict__ logits, uint32_t s,
                                             pdg::RoundKeys rk, unsigned long long *__restrict__ nacc,
                                             uint8_t *__restrict__ prop, uint8_t *__restrict__ accout,
                                             uint8_t *__restrict__ flagout)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= nb * g.C) return;  // wave-uniform
-    const int64_t b = w / g.C;
-    const int c = (int)(w - b * g.C);
+    __shared__ uint8_t xs[64][CT];
+    __shared__ uint8_t ts[32][CT];
+    __shared__ uint32_t us[CT][66];  // the tile's 65 24-bit uniforms per chain
+    __shared__ uint32_t nacc_ws[4];
+    const int64_t b = blockIdx.x;
+    const int c0 = blockIdx.y * CT, nc = min(CT, g.C - c0);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    stage_tile(g, b, c0, nc, x, xs, ts);
+    // 13 generator calls per chain, each giving five uniforms (draw d: call
+    // d / 5, slot d % 5), computed once for the tile
+    for (int q = threadIdx.x; q < nc * 13; q += 256) {
+        const int c = q / 13, k = q - 13 * c;
+        const Words wd = pdg::philox4x32_10((uint32_t)b, (uint32_t)((uint64_t)b >> 32),
+                                            (kPhaseBlock << 30) | (uint32_t)(16 * (c0 + c) + k), s, rk);
+        const int d0 = 5 * k;
+        us[c][d0] = wd.w0 >> 8;
+        us[c][d0 + 1] = wd.w1 >> 8;
+        us[c][d0 + 2] = wd.w2 >> 8;
+        us[c][d0 + 3] = wd.w3 >> 8;
+        if (d0 + 4 < 66) us[c][d0 + 4] = pdg::fifth_u24(wd);
+    }
+    __syncthreads();
     const int64_t node = block_node(g, b, lane);
-    const int xv = x[node * g.C + c];
-    const double f = block_field(g, b, c, lane, node);
-    const double l = (double)logits[w * 64 + lane];
-    // draw `lane` comes from call lane / 5, slot lane % 5
-    const int call = lane / 5, slot = lane - 5 * (lane / 5);
-    const Words wd = pdg::philox4x32_10((uint32_t)b, (uint32_t)((uint64_t)b >> 32),
-                                        (kPhaseBlock << 30) | (uint32_t)(16 * c + call), s, rk);
-    const uint32_t U = slot < 4 ? (pdg::word_at(wd, slot) >> 8) : pdg::fifth_u24(wd);
-    const double u = ((double)U + 0.5) * 0x1p-24;
-    const double p1 = 1.0 / (1.0 + exp(-l));
-    const int xp = u < p1 ? 1 : 0;
-    bool flag = fabs(u - p1) < 1e-9;
-    // draw 64 (acceptance) is slot 4 of call 12, which lanes 60..63 hold
-    const uint32_t Uacc = (uint32_t)__shfl((int)pdg::fifth_u24(wd), 60);
-    // log acceptance ratio: sum_p (x'_p - x_p)(f_p - l_p) + inside couplings
-    const int col = lane & 7, row = lane >> 3;
-    const int xr = __shfl(xv, (lane + 1) & 63), xpr = __shfl(xp, (lane + 1) & 63);
-    const int xd = __shfl(xv, (lane + 8) & 63), xpd = __shfl(xp, (lane + 8) & 63);
-    double t = (double)(xp - xv) * (f - l);
-    if (col < 7) t += g.lint[node * 2 + 0] * (double)(xp * xpr - xv * xr);
-    if (row < 7) t += g.lint[node * 2 + 1] * (double)(xp * xpd - xv * xd);
+    const double f0 = g.f0[node];
+    const LaneSlots sl = lane_slots(g, b, lane);
+    const int col = lane & 7, rowp = lane >> 3;
+    const double lr = col < 7 ? g.lint[node * 2 + 0] : 0.0;
+    const double ld = rowp < 7 ? g.lint[node * 2 + 1] : 0.0;
+    uint32_t my_acc = 0;
+    for (int c = wv; c < nc; c += 4) {
+        const int64_t row = b * g.C + c0 + c;
+        const int xv = xs[lane][c];
+        const double f = tile_field(f0, sl, ts, c);
+        const double l = (double)logits[row * 64 + lane];
+        // proposal bit: u < sigmoid(l), the sigmoid in FP32, u exact in FP64
+        const double u = ((double)us[c][lane] + 0.5) * 0x1p-24;
+        const double p1 = (double)(1.0f / (1.0f + expf(-(float)l)));
+        const int xp = u < p1 ? 1 : 0;
+        bool flag = fabs(u - p1) < 1e-6;
+        const uint32_t Uacc = us[c][64];
+        const int xr = __shfl(xv, (lane + 1) & 63), xpr = __shfl(xp, (lane + 1) & 63);
+        const int xd = __shfl(xv, (lane + 8) & 63), xpd = __shfl(xp, (lane + 8) & 63);
+        double t = (double)(xp - xv) * (f - l);
+        if (col < 7) t += lr * (double)(xp * xpr - xv * xr);
+        if (rowp < 7) t += ld * (double)(xp * xpd - xv * xd);
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
-    const double lu = log(((double)Uacc + 0.5) * 0x1p-24);
-    const bool acc = lu < t;
-    flag = flag || fabs(lu - t) < 1e-9;
-    if (acc) x[node * g.C + c] = (uint8_t)xp;
-    const bool anyflag = __ballot(flag) != 0;
-    if (prop) prop[w * 64 + lane] = (uint8_t)xp;
-    if (lane == 0) {
-        if (acc) atomicAdd(nacc, 1ull);
-        if (accout) accout[w] = acc ? 1 : 0;
-        if (flagout) flagout[w] = anyflag ? 1 : 0;
+        for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+        const double lu = log(((double)Uacc + 0.5) * 0x1p-24);
+        const bool acc = lu < t;
+        flag = flag || fabs(lu - t) < 1e-9;
+        if (acc) xs[lane][c] = (uint8_t)xp;
+        const bool anyflag = __ballot(flag) != 0;
+        if (prop) prop[row * 64 + lane] = (uint8_t)xp;
+        if (lane == 0) {
+            my_acc += acc ? 1u : 0u;
+            if (accout) accout[row] = acc ? 1 : 0;
+            if (flagout) flagout[row] = anyflag ? 1 : 0;
+        }
+    }
+    if (lane == 0) nacc_ws[wv] = my_acc;
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * CT; q += 256) {
+        const int p = q / CT, c = q - p * CT;
+        if (c < nc) x[block_node(g, b, p) * g.C + c0 + c] = xs[p][c];
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t tot = nacc_ws[0] + nacc_ws[1] + nacc_ws[2] + nacc_ws[3];
+        if (tot) atomicAdd(nacc, (unsigned long long)tot);
     }
 }
 
@@ -278,7 +353,6 @@ __device__ __forceinline__ void dense_relu(const uint16_t *src, const uint16_t *
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int lr = lane & 15, lk = 8 * (lane >> 4);
-#pragma unroll 2
     for (int k0 = 0; k0 < K; k0 += 32) {
         bf16x8 a[4], bb[4];
 #pragma unroll
@@ -350,7 +424,6 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const uint16_t *__restrict__ wb
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t *W3 = wbf + PDG_MLP_OFF_W3;
-#pragma unroll 2
     for (int k0 = 0; k0 < NH; k0 += 32) {
         const bf16x8 bb = *reinterpret_cast<const bf16x8 *>(W3 + (int64_t)(16 * wv + lr) * NH + k0 + lk);
 #pragma unroll
@@ -768,8 +841,8 @@ pdg_status pdg_blk_inputs(pdg_blk *b, uint16_t *d_in, uint8_t *d_target, double 
     pdg_status st = blk_view(b, &v, true);
     if (st != PDG_OK) return st;
     if (!d_in) return blk_fail(b, PDG_EINVAL, "null input buffer");
-    const int64_t waves = b->nb * b->C;
-    k_inputs<<<(unsigned)cdiv(waves, 4), 256, 0, v.stream>>>(geo(b), b->nb, v.d_x, d_in, d_target, d_fields);
+    k_inputs<<<dim3((unsigned)b->nb, (unsigned)cdiv(b->C, CT)), 256, 0, v.stream>>>(geo(b), v.d_x, d_in,
+                                                                                   d_target, d_fields);
     BLK_HIP(b, hipGetLastError());
     return PDG_OK;
 }
@@ -781,12 +854,11 @@ pdg_status pdg_blk_mh(pdg_blk *b, const float *d_logits, uint8_t *d_prop, uint8_
     if (st != PDG_OK) return st;
     if (!d_logits) return blk_fail(b, PDG_EINVAL, "null logits");
     if (b->s == 0) return blk_fail(b, PDG_ESTATE, "pdg_blk_cut_duals first");
-    const int64_t waves = b->nb * b->C;
-    k_mh<<<(unsigned)cdiv(waves, 4), 256, 0, v.stream>>>(geo(b), b->nb, v.d_x, d_logits, (uint32_t)b->s,
-                                                           pdg::make_round_keys(v.seed), b->d_nacc, d_prop,
-                                                           d_acc, d_flag);
+    k_mh<<<dim3((unsigned)b->nb, (unsigned)cdiv(b->C, CT)), 256, 0, v.stream>>>(
+        geo(b), v.d_x, d_logits, (uint32_t)b->s, pdg::make_round_keys(v.seed), b->d_nacc, d_prop, d_acc,
+        d_flag);
     BLK_HIP(b, hipGetLastError());
-    b->proposed += waves;
+    b->proposed += b->nb * b->C;
     return PDG_OK;
 }
 

@@ -2,9 +2,9 @@
 blocking (``-m gpu``), through the C ABI.
 
 Bars.  Cut duals, proposals, acceptances and new states: bit-exact except
-flagged draws (uniform within 1e-6 of p(theta = 0) for a dual, within 1e-9 of
-sigmoid(l) for a proposal bit, log u within 1e-9 of the log acceptance ratio),
-which must be rare.  Fields: FP64, within 1e-12 (1 + |f|) (the same sums in
+flagged draws (uniform within 1e-6 of p(theta = 0) for a dual or of sigmoid(l)
+for a proposal bit, log u within 1e-9 of the log acceptance ratio), which must
+be rare (a proposal row holds 64 draws, so about 1.3e-4 of rows are flagged).  Fields: FP64, within 1e-12 (1 + |f|) (the same sums in
 another order).  Network: each layer teacher-forced from the GPU's previous
 layer; a layer's FP32 accumulation of K products differs from FP64 by at most
 gamma_K sum |w a| (gamma_K = K u / (1 - K u), u = 2^-24), so a BF16 activation
@@ -287,7 +287,7 @@ def test_block_step_matches_oracle(H, Wd, C, dtype):
         tot["rows"] += rows
         tot["accepted"] += int(acc_o.sum())
     _say(f"  {H}x{Wd} C={C} {dtype}: {tot}")
-    assert tot["flag_rows"] <= max(1e-3 * tot["rows"], 2)
+    assert tot["flag_rows"] <= max(2e-3 * tot["rows"], 3)
     assert tot["dflag"] <= max(1e-5 * tot["duals"], 2)
     s_info = pb.pdg_blk_info(bp.blk, s.ctx)
     assert s_info[0] == 4 and s_info[3] == 4 * rows
