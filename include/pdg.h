@@ -188,6 +188,23 @@ pdg_status pdg_get_marginals(pdg_ctx *ctx, double *d_out, int64_t *h_samples);
 pdg_status pdg_get_counts(pdg_ctx *ctx, uint32_t *d_out, int64_t *h_samples);
 pdg_status pdg_reset_marginals(pdg_ctx *ctx);
 
+/* Replayed sweeps (HIP graphs).  pdg_graph_create captures n_sweeps full
+ * sweeps (1..4096) of each of n_ctx contexts (same device and stream; for
+ * example one context per state count of a batch of graphs) into one graph:
+ * per sweep and context a one-thread kernel advancing that context's sweep
+ * counter in device memory, then its dual and primal phase kernels, which read
+ * the counter (and whether the sweep is counted) from there.  The graph holds
+ * no memset or copy.  pdg_graph_launch sets each counter to the context's t
+ * and replays the graph on the contexts' stream: the same draws as n_sweeps
+ * pdg_sweep calls of each context, in phase launches (never the one-launch
+ * form of small graphs).  A graph whose contexts have been edited since the
+ * capture is refused (PDG_ESTATE); capture again.  The graph keeps the
+ * contexts' buffer addresses: destroy it before the contexts. */
+typedef struct pdg_graph pdg_graph;
+pdg_status pdg_graph_create(pdg_ctx *const *ctxs, int32_t n_ctx, int32_t n_sweeps, pdg_graph **out);
+pdg_status pdg_graph_launch(pdg_graph *graph);
+pdg_status pdg_graph_destroy(pdg_graph *graph);
+
 /* Wait for the context's stream and report any asynchronous kernel error. */
 pdg_status pdg_sync(pdg_ctx *ctx);
 /* Message of the last failure on ctx (valid until the next call on ctx);

@@ -86,6 +86,8 @@ struct pdg_ctx {
     int64_t part_cap = 0;        // doubles
     bool broken = false;         // an edit failed after it began to change the store
     void *d_static = nullptr;    // this device's copy of the static workspace (pdg_log_v_noalloc)
+    uint64_t gen = 0;            // edge-store generation: advanced by every edit
+    bool replay = false;         // launches are being captured for replay (device counter)
     std::string err;
 };
 
@@ -232,6 +234,10 @@ static Graph make_graph(pdg_ctx *ctx)
     g.k0 = (uint32_t)ctx->cfg.seed;
     g.k1 = (uint32_t)(ctx->cfg.seed >> 32);
     g.rk = make_round_keys(ctx->cfg.seed);
+    // while sweeps are captured for replay the kernels read the sweep counter
+    // from word 8 of the flag block, which the captured tick kernel advances
+    g.tsrc = ctx->replay ? ctx->d_flag + 8 : nullptr;
+    g.burn = ctx->cfg.burn_in;
     return g;
 }
 
@@ -1052,6 +1058,7 @@ pdg_status pdg_insert_edges(pdg_ctx *ctx, int64_t m, const int32_t *d_src, const
     PDG_TRY(read_sum(ctx, &h));
     ctx->hwm = h.hwm;
     ctx->broken = false;
+    ctx->gen++;
     return PDG_OK;
 }
 
@@ -1097,6 +1104,7 @@ pdg_status pdg_remove_edges(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid)
     ctx->live -= m;
     PDG_HIP(ctx, hipStreamSynchronize(st));
     ctx->broken = false;
+    ctx->gen++;
     return PDG_OK;
 }
 
@@ -1277,6 +1285,121 @@ pdg_status pdg_sweep(pdg_ctx *ctx, int64_t n_sweeps)
         PDG_TRY(pdg_dual_phase(ctx));
         PDG_TRY(pdg_primal_phase(ctx));
     }
+    return PDG_OK;
+}
+
+struct pdg_graph {
+    std::vector<pdg_ctx *> ctxs;
+    std::vector<uint64_t> gens;
+    int32_t n_sweeps = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+pdg_status pdg_graph_create(pdg_ctx *const *ctxs, int32_t n_ctx, int32_t n_sweeps, pdg_graph **out)
+{
+    if (!ctxs || !out || n_ctx < 1) return fail(nullptr, PDG_EINVAL, "bad argument");
+    *out = nullptr;
+    if (n_sweeps < 1 || n_sweeps > 4096) return fail(nullptr, PDG_EINVAL, "n_sweeps must be in [1, 4096]");
+    for (int32_t i = 0; i < n_ctx; ++i) {
+        pdg_ctx *c = ctxs[i];
+        if (!c) return fail(nullptr, PDG_EINVAL, "null context");
+        if (!c->nodes_set) return fail(nullptr, PDG_ESTATE, "pdg_set_nodes first");
+        if (c->phase != 0) return fail(nullptr, PDG_ESTATE, "capture between sweeps");
+        if (c->device != ctxs[0]->device || c->stream != ctxs[0]->stream)
+            return fail(nullptr, PDG_EINVAL, "every context of a graph needs the same device and stream");
+        for (int32_t j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(nullptr, PDG_EINVAL, "a context appears twice");
+    }
+    if (ctxs[0]->broken || hipSetDevice(ctxs[0]->device) != hipSuccess)
+        return fail(nullptr, PDG_ESTATE, "context unusable");
+    pdg_graph *gr = new (std::nothrow) pdg_graph();
+    if (!gr) return fail(nullptr, PDG_ENOMEM, "host allocation failed");
+    gr->ctxs.assign(ctxs, ctxs + n_ctx);
+    for (pdg_ctx *c : gr->ctxs) gr->gens.push_back(c->gen);
+    gr->n_sweeps = n_sweeps;
+    // capture on a stream of our own (the contexts' stream may be the legacy
+    // default stream, which cannot be captured); replays go to theirs
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        delete gr;
+        return fail(nullptr, PDG_EHIP, "hipStreamCreateWithFlags failed");
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    std::vector<hipStream_t> saved;
+    for (pdg_ctx *c : gr->ctxs) {
+        saved.push_back(c->stream);
+        c->stream = cs;
+        c->replay = true;
+    }
+    if (e == hipSuccess) {
+        for (int32_t k = 0; k < n_sweeps && e == hipSuccess; ++k)
+            for (pdg_ctx *c : gr->ctxs) {
+                k_tick<<<1, 64, 0, cs>>>(c->d_flag + 8);
+                launch_dual(c, 0u);
+                launch_primal(c, 0u, 0);
+                e = hipGetLastError();
+                if (e != hipSuccess) break;
+            }
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e2;
+        gr->graph = graph;
+    }
+    for (size_t i = 0; i < gr->ctxs.size(); ++i) {
+        gr->ctxs[i]->stream = saved[i];
+        gr->ctxs[i]->replay = false;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+        if (gr->graph) (void)hipGraphDestroy(gr->graph);
+        delete gr;
+        return fail(nullptr, PDG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *out = gr;
+    return PDG_OK;
+}
+
+pdg_status pdg_graph_launch(pdg_graph *gr)
+{
+    if (!gr) return fail(nullptr, PDG_EINVAL, "null graph");
+    const int64_t n = gr->n_sweeps;
+    for (size_t i = 0; i < gr->ctxs.size(); ++i) {
+        pdg_ctx *c = gr->ctxs[i];
+        if (c->gen != gr->gens[i])
+            return fail(nullptr, PDG_ESTATE, "the edges changed since the sweeps were captured; capture again");
+        if (c->phase != 0) return fail(nullptr, PDG_ESTATE, "replay between sweeps");
+        if (c->t + n >= 0xFFFFFFFFll) return fail(nullptr, PDG_ECAPACITY, "sweep counter exhausted");
+        const int64_t first = std::max<int64_t>(c->t + 1, c->cfg.burn_in + 1);
+        const int64_t counted = std::max<int64_t>(0, c->t + n - first + 1);
+        if (counted && (uint64_t)(c->counted + counted) * (uint64_t)c->C > 0xFFFFFFFFull)
+            return fail(nullptr, PDG_ECAPACITY, "marginal counters would overflow; read and reset them");
+    }
+    pdg_ctx *c0 = gr->ctxs[0];
+    for (pdg_ctx *c : gr->ctxs)
+        if (c->broken) return fail(nullptr, PDG_ESTATE, "a context of the graph is unusable");
+    PDG_HIP(nullptr, hipSetDevice(c0->device));
+    for (pdg_ctx *c : gr->ctxs)
+        k_set_counter<<<1, 64, 0, c0->stream>>>(c->d_flag + 8, (uint32_t)c->t);
+    PDG_HIP(nullptr, hipGetLastError());
+    PDG_HIP(nullptr, hipGraphLaunch(gr->exec, c0->stream));
+    for (pdg_ctx *c : gr->ctxs) {
+        const int64_t first = std::max<int64_t>(c->t + 1, c->cfg.burn_in + 1);
+        c->counted += std::max<int64_t>(0, c->t + n - first + 1);
+        c->t += n;
+    }
+    return PDG_OK;
+}
+
+pdg_status pdg_graph_destroy(pdg_graph *gr)
+{
+    if (!gr) return PDG_OK;
+    if (!gr->ctxs.empty()) (void)hipSetDevice(gr->ctxs[0]->device);
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
     return PDG_OK;
 }
 

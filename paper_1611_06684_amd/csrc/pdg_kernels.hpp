@@ -92,7 +92,25 @@ struct Graph {
                                           // drawn by the hub kernels (0: none)
     uint32_t k0, k1;                      // generator key
     RoundKeys rk;                         // its ten round keys
+    const uint32_t *tsrc;                 // replayed sweeps: the sweep counter in device
+                                          // memory (null: the kernel argument t)
+    int64_t burn;                         // counting starts after this sweep (with tsrc)
 };
+
+// Sweep counter of a phase kernel: the argument, or, in sweeps replayed from a
+// captured HIP graph, the device counter the graph's tick kernel advances (and
+// then whether this sweep is counted in the marginals).
+__device__ __forceinline__ void sweep_args(const Graph &g, uint32_t &t, int &count)
+{
+    if (g.tsrc) {
+        t = __builtin_amdgcn_readfirstlane(*g.tsrc);
+        count = (int64_t)t > g.burn ? 1 : 0;
+    }
+}
+__device__ __forceinline__ void sweep_args(const Graph &g, uint32_t &t)
+{
+    if (g.tsrc) t = __builtin_amdgcn_readfirstlane(*g.tsrc);
+}
 
 __host__ __device__ constexpr int rec_len(int qm) { return dim_d(qm); }
 // u32 words of dual masks per incidence record
@@ -436,6 +454,7 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
 template <int QM, int LPI, bool UQ>
 __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
 {
+    sweep_args(g, t);
     dual_wave<QM, LPI, UQ>(g, t, LaneMap<LPI>(g.C));
 }
 
@@ -453,6 +472,7 @@ template <int LPI, bool UQ, int E>
 __global__ __launch_bounds__(256) void k_dual_bin(Graph g, uint32_t t)
 {
     static_assert(LPI == 8 || LPI == 16, "binary dual: 8 or 16 chains per item");
+    sweep_args(g, t);
     constexpr int P = 64 / LPI;
     constexpr uint32_t WMASK = (1u << LPI) - 1u;
     const int lane = threadIdx.x & 63;
@@ -546,6 +566,7 @@ struct DualParams {
 template <int QM, bool UQ, int E>
 __global__ __launch_bounds__(256) void k_dual64(Graph g, uint32_t t)
 {
+    sweep_args(g, t);
     constexpr int D = dim_d(QM);
     constexpr int NCALL = (D + 4) / 5;
     constexpr int NW = 2 * D;  // mask half-words of one edge
@@ -733,6 +754,7 @@ template <int QM, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QM <= 5 ? 8 : 1))) void k_primal64(
     Graph g, uint32_t t, int count)
 {
+    sweep_args(g, t, count);
     constexpr int D = dim_d(QM);
     constexpr int RP = rec_len(QM);                         // doubles per record
     constexpr int NLD = D <= 16 ? 1 : 2;                    // 16-byte loads per lane and node
@@ -893,6 +915,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QM <= 5 ? 8
 template <int QM, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count)
 {
+    sweep_args(g, t, count);
     constexpr int D = dim_d(QM);
     constexpr int RP = rec_len(QM);
     constexpr int BUF = 3072;                                 // LDS bytes per buffer (two per wave)
@@ -1191,6 +1214,7 @@ __global__ __launch_bounds__(256) void k_hub_finish(Graph g, int64_t nh,
                                                     const double *__restrict__ part, uint32_t t,
                                                     int count)
 {
+    sweep_args(g, t, count);
     const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) +
                       __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1325,6 +1349,7 @@ __device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int coun
 template <int QM, int LPI, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) void k_primal(Graph g, uint32_t t, int count)
 {
+    sweep_args(g, t, count);
     primal_wave<QM, LPI, UQ, EXP64>(g, t, count, LaneMap<LPI>(g.C));
 }
 
@@ -1348,6 +1373,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UQ && QM <=
     Graph g, uint32_t t, int count)
 {
     static_assert(LPI == 8 || LPI == 16, "staged generic primal: 8 or 16 chains per item");
+    sweep_args(g, t, count);
     constexpr int D = dim_d(QM);
     static_assert(rec_len(QM) == D, "one h per entry");
     constexpr int P = 64 / LPI;      // quads per wave
@@ -1701,6 +1727,17 @@ __global__ __launch_bounds__(1024) void k_sweeps_lds(Graph g, uint32_t t0, int32
 // ---------------------------------------------------------------------------
 // Small kernels: edits, readout.
 // ---------------------------------------------------------------------------
+// The device sweep counter of replayed sweeps: set before a replay, advanced
+// by one at the start of each captured sweep.
+__global__ void k_tick(uint32_t *t)
+{
+    if (threadIdx.x == 0) *t += 1u;
+}
+__global__ void k_set_counter(uint32_t *t, uint32_t v)
+{
+    if (threadIdx.x == 0) *t = v;
+}
+
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

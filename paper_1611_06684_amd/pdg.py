@@ -28,7 +28,7 @@ EXPORTS = [
     "pdg_set_state", "pdg_get_state", "pdg_get_sweep", "pdg_set_sweep", "pdg_sweep",
     "pdg_dual_phase", "pdg_primal_phase", "pdg_get_duals", "pdg_get_marginals",
     "pdg_get_counts", "pdg_reset_marginals", "pdg_sync", "pdg_last_error", "pdg_log_v",
-    "pdg_log_v_noalloc",
+    "pdg_log_v_noalloc", "pdg_graph_create", "pdg_graph_launch", "pdg_graph_destroy",
 ]
 
 
@@ -81,6 +81,9 @@ def lib():
             "pdg_get_duals": ([_P, _I64, _P, _P], S),
             "pdg_log_v": ([_P, _P], S),
             "pdg_log_v_noalloc": ([_P, _P], S),
+            "pdg_graph_create": ([ctypes.POINTER(_P), _I32, _I32, ctypes.POINTER(_P)], S),
+            "pdg_graph_launch": ([_P], S),
+            "pdg_graph_destroy": ([_P], S),
             "pdg_get_marginals": ([_P, _P, ctypes.POINTER(_I64)], S),
             "pdg_get_counts": ([_P, _P, ctypes.POINTER(_I64)], S),
             "pdg_reset_marginals": ([_P], S),
@@ -192,6 +195,21 @@ def pdg_log_v(ctx, d_out):
 
 def pdg_log_v_noalloc(ctx, d_out):
     _chk(lib().pdg_log_v_noalloc(ctx, d_out), ctx)
+
+
+def pdg_graph_create(ctxs, n_sweeps):
+    arr = (_P * len(ctxs))(*[c.value if isinstance(c, _P) else c for c in ctxs])
+    out = _P()
+    _chk(lib().pdg_graph_create(arr, len(ctxs), n_sweeps, ctypes.byref(out)))
+    return out
+
+
+def pdg_graph_launch(graph):
+    _chk(lib().pdg_graph_launch(graph))
+
+
+def pdg_graph_destroy(graph):
+    _chk(lib().pdg_graph_destroy(graph))
 
 
 def pdg_get_marginals(ctx, d_out) -> int:
