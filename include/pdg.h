@@ -205,6 +205,34 @@ pdg_status pdg_graph_create(pdg_ctx *const *ctxs, int32_t n_ctx, int32_t n_sweep
 pdg_status pdg_graph_launch(pdg_graph *graph);
 pdg_status pdg_graph_destroy(pdg_graph *graph);
 
+/* Launch parameters of the sweep kernels.  None of them changes a draw's
+ * generator values; the dual's tiling changes no result at all, the hub split
+ * changes the order in which a hub's field is summed (FP64 rounding only).
+ *   dual_edges_per_wave     2, 4 or 8: edges one wave of the 33+-chain dual takes
+ *   binary_groups_per_wave  2, 4 or 8: item groups per wave of the binary dual
+ *                           (q_max 2, 8 or 16 chains)
+ *   hub_threshold           nodes with more incidence entries are split into
+ *                           pieces for the hub kernels (0: never)
+ *   hub_piece               records per piece
+ * pdg_tune times each dual tiling and each hub setting (thresholds 0, 128,
+ * 256, 512, 1024; pieces 64, 128, 256) on the current graph with `reps`
+ * launches each, keeps the fastest and reports the times in dual_ms and
+ * primal_ms (per launch).  It runs dual and primal phases without counting and
+ * restores x afterwards: the chain, its sweep counter and the counters are as
+ * before.  It allocates a copy of x.  pdg_set_tuning applies given values
+ * (PDG_EINVAL out of range); both refuse between the phases and make captured
+ * graphs stale. */
+typedef struct {
+    int32_t dual_edges_per_wave;
+    int32_t binary_groups_per_wave;
+    int32_t hub_threshold;
+    int32_t hub_piece;
+    float dual_ms, primal_ms;  /* pdg_tune's measurements (-1 otherwise) */
+} pdg_tuning;
+pdg_status pdg_tune(pdg_ctx *ctx, int32_t reps, pdg_tuning *h_out);
+pdg_status pdg_set_tuning(pdg_ctx *ctx, const pdg_tuning *h_in);
+pdg_status pdg_get_tuning(pdg_ctx *ctx, pdg_tuning *h_out);
+
 /* Wait for the context's stream and report any asynchronous kernel error. */
 pdg_status pdg_sync(pdg_ctx *ctx);
 /* Message of the last failure on ctx (valid until the next call on ctx);

@@ -87,6 +87,11 @@ struct pdg_ctx {
     bool broken = false;         // an edit failed after it began to change the store
     void *d_static = nullptr;    // this device's copy of the static workspace (pdg_log_v_noalloc)
     uint64_t gen = 0;            // edge-store generation: advanced by every edit
+    // launch parameters (pdg_tune / pdg_set_tuning): edges per wave of the
+    // 33+-chain dual, item groups per wave of the binary dual, hub threshold
+    // (0: hubs not split) and records per hub piece
+    int32_t tune_e64 = 4, tune_ebin = 4;
+    uint32_t tune_hub_thr = 256, tune_piece = 128;
     bool replay = false;         // launches are being captured for replay (device counter)
     std::string err;
 };
@@ -242,17 +247,36 @@ static Graph make_graph(pdg_ctx *ctx)
 }
 
 // ------------------------------------------------------------- kernel dispatch
+template <int QM, bool UQ, int E>
+static void dual64_e(const Graph &g, uint32_t t, int CB, hipStream_t s)
+{
+    const int64_t waves = cdiv(g.hwm, E) * CB;
+    k_dual64<QM, UQ, E><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+}
+
+template <int LPI, bool UQ, int E>
+static void dual_bin_e(const Graph &g, uint32_t t, hipStream_t s)
+{
+    constexpr int P = 64 / LPI;
+    const int64_t waves = cdiv(cdiv(g.hwm, P), E);
+    k_dual_bin<LPI, UQ, E><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+}
+
 template <int QM, int LPI, bool UQ>
-static void launch_dual_t(const Graph &g, uint32_t t, int CB, hipStream_t s)
+static void launch_dual_t(const Graph &g, uint32_t t, int CB, hipStream_t s, int e64, int ebin)
 {
     if constexpr (LPI == 64) {
-        constexpr int E = kDualEdgesPerWave;
-        const int64_t waves = cdiv(g.hwm, E) * CB;
-        k_dual64<QM, UQ, E><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+        switch (e64) {
+        case 2: dual64_e<QM, UQ, 2>(g, t, CB, s); break;
+        case 8: dual64_e<QM, UQ, 8>(g, t, CB, s); break;
+        default: dual64_e<QM, UQ, 4>(g, t, CB, s); break;
+        }
     } else if constexpr (QM == 2 && (LPI == 8 || LPI == 16)) {
-        constexpr int P = 64 / LPI, E = kBinaryGroupsPerWave;
-        const int64_t waves = cdiv(cdiv(g.hwm, P), E);
-        k_dual_bin<LPI, UQ, E><<<grid_for(waves * 64), 256, 0, s>>>(g, t);
+        switch (ebin) {
+        case 2: dual_bin_e<LPI, UQ, 2>(g, t, s); break;
+        case 8: dual_bin_e<LPI, UQ, 8>(g, t, s); break;
+        default: dual_bin_e<LPI, UQ, 4>(g, t, s); break;
+        }
     } else {
         constexpr int P = 64 / LPI;
         const int64_t waves = cdiv(g.hwm, P) * CB;
@@ -282,14 +306,14 @@ static void launch_primal_t(const Graph &g, uint32_t t, int count, int CB, hipSt
 }
 
 template <int QM, bool UQ>
-static void dual_q(int lpi, const Graph &g, uint32_t t, int CB, hipStream_t s)
+static void dual_q(int lpi, const Graph &g, uint32_t t, int CB, hipStream_t s, int e64, int ebin)
 {
     switch (lpi) {
-    case 1: launch_dual_t<QM, 1, UQ>(g, t, CB, s); break;
-    case 8: launch_dual_t<QM, 8, UQ>(g, t, CB, s); break;
-    case 16: launch_dual_t<QM, 16, UQ>(g, t, CB, s); break;
-    case 32: launch_dual_t<QM, 32, UQ>(g, t, CB, s); break;
-    default: launch_dual_t<QM, 64, UQ>(g, t, CB, s); break;
+    case 1: launch_dual_t<QM, 1, UQ>(g, t, CB, s, e64, ebin); break;
+    case 8: launch_dual_t<QM, 8, UQ>(g, t, CB, s, e64, ebin); break;
+    case 16: launch_dual_t<QM, 16, UQ>(g, t, CB, s, e64, ebin); break;
+    case 32: launch_dual_t<QM, 32, UQ>(g, t, CB, s, e64, ebin); break;
+    default: launch_dual_t<QM, 64, UQ>(g, t, CB, s, e64, ebin); break;
     }
 }
 
@@ -310,13 +334,13 @@ static void launch_dual_u(pdg_ctx *ctx, uint32_t t)
 {
     const Graph g = make_graph(ctx);
     switch (ctx->QM) {
-    case 2: dual_q<2, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 3: dual_q<3, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 4: dual_q<4, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 5: dual_q<5, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 6: dual_q<6, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    case 7: dual_q<7, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
-    default: dual_q<8, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream); break;
+    case 2: dual_q<2, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream, ctx->tune_e64, ctx->tune_ebin); break;
+    case 3: dual_q<3, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream, ctx->tune_e64, ctx->tune_ebin); break;
+    case 4: dual_q<4, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream, ctx->tune_e64, ctx->tune_ebin); break;
+    case 5: dual_q<5, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream, ctx->tune_e64, ctx->tune_ebin); break;
+    case 6: dual_q<6, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream, ctx->tune_e64, ctx->tune_ebin); break;
+    case 7: dual_q<7, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream, ctx->tune_e64, ctx->tune_ebin); break;
+    default: dual_q<8, UQ>(ctx->LPI, g, t, ctx->CB, ctx->stream, ctx->tune_e64, ctx->tune_ebin); break;
     }
 }
 
@@ -703,10 +727,11 @@ static pdg_status rebuild_hubs(pdg_ctx *ctx, uint32_t *flag, uint32_t *pieces, u
     const int64_t zr = ctx->LPI == 64 ? 2 * D * ctx->CB : D;
     const int64_t zb = (8 * D + 15) / 16 * 16;
     const int64_t K = (4096 - zb - 48) / (RP * 8 + 4 * zr);
-    if (K < (ctx->LPI == 64 ? 1 : 64 / ctx->LPI)) return PDG_OK;
+    if (K < (ctx->LPI == 64 ? 1 : 64 / ctx->LPI) || ctx->tune_hub_thr == 0) return PDG_OK;
     const int64_t n = ctx->n;
     const hipStream_t st = ctx->stream;
-    k_hub_count<<<grid_for(n), 256, 0, st>>>(n, ctx->d_cnt, kHubThreshold, kHubPiece, flag, pieces);
+    k_hub_count<<<grid_for(n), 256, 0, st>>>(n, ctx->d_cnt, ctx->tune_hub_thr, ctx->tune_piece, flag,
+                                             pieces);
     PDG_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp, tb, flag, hidx, (int)n, st));
     PDG_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp, tb, pieces, pidx, (int)n, st));
     k_scan_total<<<1, 64, 0, st>>>(n, flag, hidx, &ctx->d_sum->nh);
@@ -731,13 +756,27 @@ static pdg_status rebuild_hubs(pdg_ctx *ctx, uint32_t *flag, uint32_t *pieces, u
         PDG_TRY(dalloc(ctx, (void **)&ctx->d_part, pd * 8));
         ctx->part_cap = pd;
     }
-    k_hub_fill<<<grid_for(n), 256, 0, st>>>(n, ctx->d_cnt, kHubPiece, flag, hidx, pidx,
+    k_hub_fill<<<grid_for(n), 256, 0, st>>>(n, ctx->d_cnt, ctx->tune_piece, flag, hidx, pidx,
                                             (uint32_t)nh, (uint32_t)np, ctx->d_hub);
     PDG_HIP(ctx, hipGetLastError());
     ctx->nh = nh;
     ctx->np = np;
-    ctx->hub_thr = kHubThreshold;
+    ctx->hub_thr = ctx->tune_hub_thr;
     return PDG_OK;
+}
+
+// rebuild_hubs with scratch of its own (tuning, explicit settings)
+static pdg_status rebuild_hubs_alone(pdg_ctx *ctx)
+{
+    const int64_t n = ctx->n;
+    const size_t tb = prim_bytes(2, n);
+    void *sp;
+    PDG_TRY(ctx_scratch(ctx, 4 * Carve::size<uint32_t>(n) + a256((int64_t)tb), &sp));
+    Carve cv{static_cast<char *>(sp)};
+    uint32_t *flag = cv.take<uint32_t>(n), *pieces = cv.take<uint32_t>(n);
+    uint32_t *hidx = cv.take<uint32_t>(n), *pidx = cv.take<uint32_t>(n);
+    void *tmp = cv.take<char>((int64_t)tb);
+    return rebuild_hubs(ctx, flag, pieces, hidx, pidx, tmp, tb);
 }
 
 struct NonZeroU64 {
@@ -837,8 +876,8 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
     }
     const int64_t N = cfg->node_capacity, S = cfg->edge_capacity;
     const int64_t N4 = (N + 3) / 4 * 4;  // segment tables are read per node quad
-    // slot arrays are read in groups of kDualEdgesPerWave slots
-    const int64_t SP = (S + kDualEdgesPerWave - 1) / kDualEdgesPerWave * kDualEdgesPerWave;
+    // slot arrays are read in groups of up to kMaxDualEdgesPerWave slots
+    const int64_t SP = (S + kMaxDualEdgesPerWave - 1) / kMaxDualEdgesPerWave * kMaxDualEdgesPerWave;
     if ((s = dalloc(ctx, (void **)&ctx->d_q, N)) ||
         (s = dalloc(ctx, (void **)&ctx->d_lam, N * ctx->QM * 8)) ||
         (s = dalloc(ctx, (void **)&ctx->d_x, N * ctx->C)) ||
@@ -1401,6 +1440,134 @@ pdg_status pdg_graph_destroy(pdg_graph *gr)
     if (gr->graph) (void)hipGraphDestroy(gr->graph);
     delete gr;
     return PDG_OK;
+}
+
+static void tuning_of(const pdg_ctx *ctx, pdg_tuning *o)
+{
+    o->dual_edges_per_wave = ctx->tune_e64;
+    o->binary_groups_per_wave = ctx->tune_ebin;
+    o->hub_threshold = (int32_t)ctx->tune_hub_thr;
+    o->hub_piece = (int32_t)ctx->tune_piece;
+}
+
+static bool tuning_valid(const pdg_tuning *t)
+{
+    auto e_ok = [](int32_t e) { return e == 2 || e == 4 || e == 8; };
+    return e_ok(t->dual_edges_per_wave) && e_ok(t->binary_groups_per_wave) &&
+           (t->hub_threshold == 0 || (t->hub_threshold >= 32 && t->hub_threshold <= (1 << 20))) &&
+           t->hub_piece >= 16 && t->hub_piece <= 4096;
+}
+
+pdg_status pdg_get_tuning(pdg_ctx *ctx, pdg_tuning *h_out)
+{
+    if (!ctx || !h_out) return fail(ctx, PDG_EINVAL, "null argument");
+    tuning_of(ctx, h_out);
+    h_out->dual_ms = h_out->primal_ms = -1.0f;
+    return PDG_OK;
+}
+
+pdg_status pdg_set_tuning(pdg_ctx *ctx, const pdg_tuning *h_in)
+{
+    if (!ctx || !h_in) return fail(ctx, PDG_EINVAL, "null argument");
+    if (!tuning_valid(h_in)) return fail(ctx, PDG_EINVAL, "tuning values out of range");
+    if (ctx->phase != 0) return fail(ctx, PDG_ESTATE, "tuning between sweeps");
+    PDG_TRY(set_dev(ctx));
+    ctx->tune_e64 = h_in->dual_edges_per_wave;
+    ctx->tune_ebin = h_in->binary_groups_per_wave;
+    ctx->tune_hub_thr = (uint32_t)h_in->hub_threshold;
+    ctx->tune_piece = (uint32_t)h_in->hub_piece;
+    if (ctx->nodes_set) PDG_TRY(rebuild_hubs_alone(ctx));
+    ctx->gen++;  // captured graphs hold the old launch shapes
+    return PDG_OK;
+}
+
+pdg_status pdg_tune(pdg_ctx *ctx, int32_t reps, pdg_tuning *h_out)
+{
+    if (!ctx || !h_out) return fail(ctx, PDG_EINVAL, "null argument");
+    if (reps < 1 || reps > 1000) return fail(ctx, PDG_EINVAL, "reps must be in [1, 1000]");
+    if (!ctx->nodes_set) return fail(ctx, PDG_ESTATE, "pdg_set_nodes first");
+    if (ctx->phase != 0) return fail(ctx, PDG_ESTATE, "tuning between sweeps");
+    PDG_TRY(set_dev(ctx));
+    const hipStream_t st = ctx->stream;
+    const int64_t nc = ctx->n * ctx->C;
+    uint8_t *xsave = nullptr;
+    PDG_TRY(dalloc(ctx, (void **)&xsave, nc));
+    hipEvent_t ea = nullptr, eb = nullptr;
+    pdg_status res = PDG_OK;
+    auto done = [&](pdg_status r) {
+        if (ea) (void)hipEventDestroy(ea);
+        if (eb) (void)hipEventDestroy(eb);
+        (void)hipFree(xsave);
+        return r;
+    };
+    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess)
+        return done(fail(ctx, PDG_EHIP, "hipEventCreate failed"));
+    if (hipMemcpyAsync(xsave, ctx->d_x, nc, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return done(fail(ctx, PDG_EHIP, "state copy failed"));
+    const uint32_t t = (uint32_t)ctx->t + 1u;
+    auto time_it = [&](auto &&launch, float *ms) -> pdg_status {
+        launch();
+        if (hipEventRecord(ea, st) != hipSuccess) return fail(ctx, PDG_EHIP, "hipEventRecord failed");
+        for (int r = 0; r < reps; ++r) launch();
+        if (hipEventRecord(eb, st) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+            hipGetLastError() != hipSuccess || hipEventElapsedTime(ms, ea, eb) != hipSuccess)
+            return fail(ctx, PDG_EHIP, "timing failed");
+        *ms /= (float)reps;
+        return PDG_OK;
+    };
+    // 1. the dual's tiling: edges per wave (33 or more chains), item groups per
+    //    wave (binary records with 8 or 16 chains); the draws do not depend on it
+    float best_d = 0.f;
+    const bool d64 = ctx->LPI == 64, dbin = ctx->QM == 2 && (ctx->LPI == 8 || ctx->LPI == 16);
+    if (ctx->hwm > 0 && (d64 || dbin)) {
+        int best_e = 4;
+        best_d = 1e30f;
+        for (int e : {2, 4, 8}) {
+            (d64 ? ctx->tune_e64 : ctx->tune_ebin) = e;
+            float ms = 0.f;
+            res = time_it([&] { launch_dual(ctx, t); }, &ms);
+            if (res != PDG_OK) return done(res);
+            if (ms < best_d) { best_d = ms; best_e = e; }
+        }
+        (d64 ? ctx->tune_e64 : ctx->tune_ebin) = best_e;
+    } else if (ctx->hwm > 0) {
+        res = time_it([&] { launch_dual(ctx, t); }, &best_d);
+        if (res != PDG_OK) return done(res);
+    } else {
+        launch_dual(ctx, t);
+    }
+    // 2. hubs: threshold and piece size of the split (the primal from the duals
+    //    just drawn, without counting; x is restored afterwards)
+    float best_p = 1e30f;
+    uint32_t bt = ctx->tune_hub_thr, bp = ctx->tune_piece;
+    const uint32_t thrs[] = {0u, 128u, 256u, 512u, 1024u};
+    const uint32_t pieces[] = {64u, 128u, 256u};
+    for (uint32_t th : thrs) {
+        for (uint32_t pc : pieces) {
+            if (th == 0 && pc != 128u) continue;
+            ctx->tune_hub_thr = th;
+            ctx->tune_piece = pc;
+            res = rebuild_hubs_alone(ctx);
+            if (res != PDG_OK) return done(res);
+            if (th != 0 && ctx->nh == 0) continue;  // no node above this threshold
+            float ms = 0.f;
+            res = time_it([&] { launch_primal(ctx, t, 0); }, &ms);
+            if (res != PDG_OK) return done(res);
+            if (ms < best_p) { best_p = ms; bt = th; bp = pc; }
+        }
+    }
+    ctx->tune_hub_thr = bt;
+    ctx->tune_piece = bp;
+    res = rebuild_hubs_alone(ctx);
+    if (res != PDG_OK) return done(res);
+    if (hipMemcpyAsync(ctx->d_x, xsave, nc, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return done(fail(ctx, PDG_EHIP, "state restore failed"));
+    ctx->gen++;
+    tuning_of(ctx, h_out);
+    h_out->dual_ms = best_d;
+    h_out->primal_ms = best_p;
+    return done(PDG_OK);
 }
 
 pdg_status pdg_get_duals(pdg_ctx *ctx, int64_t m, const uint64_t *d_uid, uint64_t *d_theta_out)

@@ -555,7 +555,8 @@ __global__ __launch_bounds__(256) void k_dual_bin(Graph g, uint32_t t)
 // load precedes every store.  Draws and mask logic are those of k_dual.
 // The slot arrays are padded to a multiple of E; free slots have uid 0.
 // ---------------------------------------------------------------------------
-constexpr int kDualEdgesPerWave = 4;
+constexpr int kDualEdgesPerWave = 4;      // default; the tuner picks 2, 4 or 8
+constexpr int kMaxDualEdgesPerWave = 8;   // slot arrays are padded to a multiple of this
 
 template <int QM>
 struct DualParams {

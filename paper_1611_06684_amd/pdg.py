@@ -29,6 +29,7 @@ EXPORTS = [
     "pdg_dual_phase", "pdg_primal_phase", "pdg_get_duals", "pdg_get_marginals",
     "pdg_get_counts", "pdg_reset_marginals", "pdg_sync", "pdg_last_error", "pdg_log_v",
     "pdg_log_v_noalloc", "pdg_graph_create", "pdg_graph_launch", "pdg_graph_destroy",
+    "pdg_tune", "pdg_set_tuning", "pdg_get_tuning",
 ]
 
 
@@ -49,6 +50,15 @@ _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
+
+
+class pdg_tuning(ctypes.Structure):
+    _fields_ = [("dual_edges_per_wave", _I32), ("binary_groups_per_wave", _I32),
+                ("hub_threshold", _I32), ("hub_piece", _I32),
+                ("dual_ms", ctypes.c_float), ("primal_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 def lib():
@@ -84,6 +94,9 @@ def lib():
             "pdg_graph_create": ([ctypes.POINTER(_P), _I32, _I32, ctypes.POINTER(_P)], S),
             "pdg_graph_launch": ([_P], S),
             "pdg_graph_destroy": ([_P], S),
+            "pdg_tune": ([_P, _I32, ctypes.POINTER(pdg_tuning)], S),
+            "pdg_set_tuning": ([_P, ctypes.POINTER(pdg_tuning)], S),
+            "pdg_get_tuning": ([_P, ctypes.POINTER(pdg_tuning)], S),
             "pdg_get_marginals": ([_P, _P, ctypes.POINTER(_I64)], S),
             "pdg_get_counts": ([_P, _P, ctypes.POINTER(_I64)], S),
             "pdg_reset_marginals": ([_P], S),
@@ -210,6 +223,22 @@ def pdg_graph_launch(graph):
 
 def pdg_graph_destroy(graph):
     _chk(lib().pdg_graph_destroy(graph))
+
+
+def pdg_tune(ctx, reps=5) -> pdg_tuning:
+    out = pdg_tuning()
+    _chk(lib().pdg_tune(ctx, reps, ctypes.byref(out)), ctx)
+    return out
+
+
+def pdg_set_tuning(ctx, tuning: pdg_tuning):
+    _chk(lib().pdg_set_tuning(ctx, ctypes.byref(tuning)), ctx)
+
+
+def pdg_get_tuning(ctx) -> pdg_tuning:
+    out = pdg_tuning()
+    _chk(lib().pdg_get_tuning(ctx, ctypes.byref(out)), ctx)
+    return out
 
 
 def pdg_get_marginals(ctx, d_out) -> int:
