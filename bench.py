@@ -134,10 +134,10 @@ def parse():
                    default="dynamic-sparse")
     p.add_argument("--epochs", type=int, default=2, help="learned workload: training epochs")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--batch-layout", choices=["by-states", "one"], default="by-states",
-                   help="batched workload: one context per state count (records sized for "
-                        "that count) or one context for the whole batch (records sized for "
-                        "the largest)")
+    p.add_argument("--batch-graphs", type=int, default=4096,
+                   help="batched workload: number of graphs (1/64 of them dense)")
+    p.add_argument("--graph-sweeps", type=int, default=10,
+                   help="batched workload: sweeps per captured HIP graph")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the run, copy a buffer of this many MiB three times (a plain "
                         "copy kernel of known size, to calibrate memory counters)")
@@ -469,43 +469,64 @@ class SamplerGroup:
 
 
 def run_batched(args):
+    """The batched workload at its full recipe: 4096 independent graphs (64 of
+    them complete binary graphs on 2048 nodes), one context per state count,
+    each tuned by pdg_tune; the timed sweeps are replays of one captured HIP
+    graph holding `graph_sweeps` sweeps of every context."""
     import torch
+    from paper_1611_06684_amd import pdg
     from paper_1611_06684_amd import workloads as W
     from paper_1611_06684_amd.pdg import Sampler
+    K = args.graph_sweeps
     steps = 50 if args.steps is None else args.steps
+    steps = max(K, (steps + K - 1) // K * K)
     warmup = 5 if args.warmup is None else args.warmup
-    C, seed, n_graphs, n_dense = 8, 0, 512, 8
-    log("building the batch")
-    model = W.batched_uneven(n_graphs, n_dense, seed=0)
-    if args.batch_layout == "by-states":
-        parts = W.group_by_states(model)
-    else:
-        parts = [(model.q_max, model)]
-    log(f"batch: {n_graphs} graphs, {model.n} nodes, {model.m} edges in "
-        f"{len(parts)} context(s); uploading and decomposing")
+    C, seed, n_graphs, n_dense = 8, 0, args.batch_graphs, max(1, args.batch_graphs // 64)
+    log(f"building the batch ({n_graphs} graphs, {n_dense} dense) per state count")
+    parts = W.batched_by_states(n_graphs, n_dense, seed=0)
+    n_nodes = sum(p.n for _, p in parts)
+    n_edges = sum(p.m for _, p in parts)
+    log(f"batch: {n_nodes} nodes, {n_edges} edges in {len(parts)} contexts; uploading")
     # distinct generator keys: the contexts' node and edge ids overlap
-    group = SamplerGroup([Sampler(p, C, seed=seed + k, burn_in=0)
-                          for k, (_, p) in enumerate(parts)])
-    for s in group.samplers:
+    samplers = [Sampler(p, C, seed=seed + k, burn_in=0) for k, (_, p) in enumerate(parts)]
+    alg = sum(dual_bytes(p, C) for _, p in parts)
+    pbytes = sum(primal_bytes(p, C) for _, p in parts)
+    sizes = [(q, p.n, p.m) for q, p in parts]
+    del parts
+    for s in samplers:
         s.init()
+    tuning = []
+    for (q, _, _), s in zip(sizes, samplers):
+        t = pdg.pdg_tune(s.ctx, 5).as_dict()
+        t["q"] = q
+        tuning.append(t)
+    log(f"tuned: {tuning}")
+    group = SamplerGroup(samplers)
     for _ in range(warmup):
         group.dual_phase()
         group.primal_phase()
     stream = torch.cuda.current_stream()
-    total_ms, dual_ms, primal_ms, wall = timed_sweeps(group, steps, stream)
-    for s in group.samplers:
+    # per-phase times from eager launches (HIP events around each phase)
+    _, dual_ms, primal_ms, _ = timed_sweeps(group, 10, stream)
+    graph = pdg.pdg_graph_create([s.ctx for s in samplers], K)
+    pdg.pdg_graph_launch(graph)  # warm
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(steps // K):
+        pdg.pdg_graph_launch(graph)
+    b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = a.elapsed_time(b)
+    pdg.pdg_graph_destroy(graph)
+    for s in samplers:
         s.sync()
         s.close()
-    updates = C * (model.n + model.m)
-    by_states = args.batch_layout == "by-states"
-    # the dual phase (all its launches) against the HBM roof: its loads and
-    # stores are scattered over records and parameter blocks, and its VALU work
-    # (Philox) is a small fraction of the issue rate
-    alg = sum(dual_bytes(p, C) for _, p in parts)
+    updates = C * (n_nodes + n_edges)
     achieved = alg / (dual_ms / 1e3) / 1e9
-    kernels = "dual phase: " + ", ".join(
-        ("k_dual_bin<8,true,4>" if q == 2 else f"k_dual<{q},8,true>") if by_states
-        else f"k_dual<{q},8,false>" for q, _ in parts)
+    p_gbs = pbytes / (primal_ms / 1e3) / 1e9
     out = {
         "metric": "chain*(|V|+|E|) updates/s", "value": updates * steps / (total_ms / 1e3),
         "unit": "updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -513,15 +534,22 @@ def run_batched(args):
         "vs_baseline": None, "dtype": DTYPE, "data": "synthetic",
         "config": {"workload": f"batched uneven: {n_graphs} graphs ({n_dense} dense binary "
                                f"N=2048), q in {{2,3,5}}, FP32 tables, {C} chains",
-                   "layout": (f"one context per state count ({len(parts)})"
-                              if args.batch_layout == "by-states" else "one context"),
-                   "nodes": model.n, "edges": model.m, "chains": C, "seed": seed,
-                   "dual_ms": dual_ms, "primal_ms": primal_ms, "wall_s": wall},
+                   "layout": f"one context per state count ({len(samplers)}), sweeps replayed "
+                             f"from one HIP graph of {K} sweeps of every context",
+                   "contexts": [{"q": q, "nodes": n, "edges": m} for q, n, m in sizes],
+                   "nodes": n_nodes, "edges": n_edges, "chains": C, "seed": seed,
+                   "tuning": tuning, "dual_ms_eager": dual_ms, "primal_ms_eager": primal_ms,
+                   "wall_s": wall, "kernel_sources": kernel_digest()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (profile_traffic("batched_uneven_sweep_kernels.txt", "dual_phase")
-                                 if by_states else None),
-                     "algorithmic_bytes": alg, "kernel": kernels},
+                     "traffic": profile_traffic("batched_uneven_sweep_kernels.txt", "dual_phase"),
+                     "algorithmic_bytes": alg, "kernel": "dual phase (one launch per state count)"},
+        "roofline_primal": {"bound": "hbm", "achieved": p_gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": p_gbs / HBM_PEAK_GBS,
+                            "traffic": profile_traffic("batched_uneven_sweep_kernels.txt",
+                                                       "primal_phase"),
+                            "kernel": "primal phase (per state count, with hub kernels)",
+                            "algorithmic_bytes": pbytes},
     }
     if not args.no_cpu_baseline:
         small = W.batched_uneven(16, 1, seed=0)

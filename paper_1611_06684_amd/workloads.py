@@ -223,6 +223,52 @@ def batched_uneven(n_graphs: int, n_dense: int, seed: int = 0, n_min: int = 100,
                  np.concatenate(dsts), np.concatenate(Lams), f"batch_{n_graphs}",
                  {"node_off": np.array(node_off), "edge_off": np.array(edge_off)})
 
+def batched_by_states(n_graphs: int, n_dense: int, seed: int = 0, n_min: int = 100,
+                      n_max: int = 50000, dense_n: int = 2048, dtype: str = "f32") -> list:
+    """The batch of ``batched_uneven`` (same recipe, same draws in the same
+    order) built directly as one model per state count, tables q x q, so no
+    table is padded to the largest q.  Returns [(q, model)] in increasing q with
+    ``meta["graphs"]`` the batch indices of each model's graphs; equal to
+    ``group_by_states(batched_uneven(...))`` for the same arguments."""
+    rng = np.random.default_rng(seed)
+    dt = _np_dtype(dtype)
+    parts = {}
+    for g in range(n_graphs):
+        if g < n_dense:
+            N, q = dense_n, 2
+            iu, ju = np.triu_indices(N, 1)
+            J = rng.normal(0.0, 0.5 / np.sqrt(N), size=iu.shape[0])
+            s = np.array([-1.0, 1.0], dtype=dt)
+            L = J.astype(dt)[:, None, None] * s[None, :, None] * s[None, None, :]
+            src, dst = iu, ju
+        else:
+            N = int(np.exp(rng.uniform(np.log(n_min), np.log(n_max))))
+            d = int(rng.integers(3, 13))
+            q = int(rng.choice([2, 3, 5]))
+            M = N * d // 2
+            src = rng.integers(0, N, size=M)
+            dst = rng.integers(0, N, size=M)
+            dst = np.where(src == dst, (dst + 1) % N, dst)
+            L = rng.normal(0.0, 0.2, size=(M, q, q)).astype(dt)
+        lam = rng.normal(0.0, 1.0, size=(N, q)).astype(dt)
+        p = parts.setdefault(q, {"n": 0, "src": [], "dst": [], "Lam": [], "lam": [], "graphs": []})
+        p["src"].append((src + p["n"]).astype(np.int32))
+        p["dst"].append((dst + p["n"]).astype(np.int32))
+        p["Lam"].append(L)
+        p["lam"].append(lam)
+        p["graphs"].append(g)
+        p["n"] += N
+    out = []
+    for q in sorted(parts):
+        p = parts[q]
+        out.append((q, Model(np.full(p["n"], q, np.int32), np.concatenate(p["lam"]),
+                             np.concatenate(p["src"]), np.concatenate(p["dst"]),
+                             np.concatenate(p["Lam"]), f"batch_{n_graphs}_q{q}",
+                             {"graphs": np.array(p["graphs"])})))
+        parts[q] = None
+    return out
+
+
 def group_by_states(batch: Model) -> list:
     """Splits a batch of independent graphs (``meta`` with ``node_off`` and
     ``edge_off``, every node of a graph with the same state count) into one

@@ -94,3 +94,18 @@ def test_dual_bytes_counts_each_edge_by_its_states():
     C = 8
     Ds = [1 * 2, 2 * 4, 4 * 4, 1 * 4]
     assert bench.dual_bytes(m, C) == sum(32 + 2 * C + 16 * d for d in Ds)
+
+
+def test_batch_by_states_equals_grouped_batch():
+    """The per-state-count batch generator draws the same graphs, tables and
+    unaries as the padded one-model batch split by state count."""
+    from paper_1611_06684_amd import workloads as W
+    for args in [(30, 2, 1, 20, 300, 40), (12, 1, 5, 100, 2000, 64)]:
+        a = W.group_by_states(W.batched_uneven(*args[:3], n_min=args[3], n_max=args[4],
+                                               dense_n=args[5]))
+        b = W.batched_by_states(*args[:3], n_min=args[3], n_max=args[4], dense_n=args[5])
+        assert [q for q, _ in a] == [q for q, _ in b]
+        for (q, x), (_, y) in zip(a, b):
+            for f in ("q", "lam", "src", "dst", "Lam"):
+                assert np.array_equal(getattr(x, f), getattr(y, f)), (q, f)
+            assert np.array_equal(x.meta["graphs"], y.meta["graphs"])
