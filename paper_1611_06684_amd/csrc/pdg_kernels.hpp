@@ -903,15 +903,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QM <= 5 ? 8
     }
 }
 
+// Counters of a node quad when each lane holds two chains (k_primal32):
+// count_quad with the two chains' draws added.
+template <int QM>
+__device__ __forceinline__ void count_quad2(uint32_t *__restrict__ counts, int64_t quad,
+                                            const int (&nx1)[4], const int (&nx2)[4],
+                                            const int (&qn)[4], uint32_t drawn, bool ch1,
+                                            bool ch2, int lane)
+{
+    uint32_t *cq = counts + quad * 4 * QM;
+    uint32_t row = 0;
+    uint64_t wmask = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool dj = (drawn >> j) & 1u;
+#pragma unroll
+        for (int a = 0; a < QM; ++a) {
+            const uint32_t add = (uint32_t)__popcll(__ballot(dj && ch1 && nx1[j] == a)) +
+                                 (uint32_t)__popcll(__ballot(dj && ch2 && nx2[j] == a));
+            row = pdg_writelane_i32(cq[j * QM + a] + add, j * QM + a, row);
+        }
+        if (dj) wmask |= ((1ull << qn[j]) - 1ull) << (j * QM);
+    }
+    if (lane_bit(wmask)) cq[lane] = row;
+}
+
 // ---------------------------------------------------------------------------
-// a4 + a5 with 17..32 chains: a wave takes one node quad; lane (p, c) is half
-// p of the wave and chain c.  The two halves walk alternate records of the
-// same node (record k + p of each pair) and add their partial fields with one
-// cross-half exchange before the draw, so all 64 lanes work although a record
-// only covers 32 chains.  The quad's records are walked as one stream of
-// chunks (a chunk: up to K records of one node, their h values and 32-bit
-// mask words); the next chunk is loaded into registers while the current one
-// is read from the wave's LDS buffer, then written to the other buffer.
+// a4 + a5 with 17..32 chains: a wave takes one node quad; lane (g, l) is in
+// record group g = lane / 16 and holds chains l and l + 16.  The four groups
+// walk records k + g of the same node, so every h and mask word read from
+// LDS serves two chains per lane (the LDS traffic per chain and entry is half
+// that of one chain per lane, which bounded this kernel), and add their
+// partial fields with a two-step butterfly before the draw (every group ends
+// with the same sums).  The quad's records are walked as one stream of chunks
+// (a chunk: up to K records of one node, their h values and 32-bit mask
+// words); the next chunk is loaded into registers while the current one is
+// read from the wave's LDS buffer, then written to the other buffer.
 // ---------------------------------------------------------------------------
 template <int QM, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count)
@@ -919,20 +946,21 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
     sweep_args(g, t, count);
     constexpr int D = dim_d(QM);
     constexpr int RP = rec_len(QM);
-    constexpr int BUF = 3072;                                 // LDS bytes per buffer (two per wave)
+    constexpr int G = 4;                                      // record groups per wave
+    constexpr int BUF = 4864;                                 // LDS bytes per buffer (two per wave)
     constexpr int ZB = (4 * D + 15) / 16 * 16;                // zero mask block (once per wave)
     constexpr int K = (BUF - 32) / (8 * RP + 4 * D);          // records per chunk
-    static_assert(K >= 2, "chunk too small");
+    static_assert(K >= G, "chunk too small");
     constexpr int HB = (16 + 8 * RP * K + 15) / 16 * 16;      // h part of a buffer
     constexpr int NH = (HB + 1023) / 1024;                    // 16-byte loads per lane, h part
     constexpr int NZ = (16 + 4 * D * K + 1023) / 1024;        // and mask part
-    static_assert(HB + 16 * 64 * NZ <= BUF + 16 * 64 * NZ, "layout");
     __shared__ __align__(16) uint8_t lds[4][2 * BUF + ZB];
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t quad = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
-    const int p = lane >> 5, c = lane & 31;
-    const bool cvalid = c < g.C;
+    const int grp = lane >> 4;
+    const int c1 = lane & 15, c2 = c1 + 16;
+    const bool cv1 = c1 < g.C, cv2 = c2 < g.C;
     if (quad * 4 >= g.n) return;
     uint32_t off[4], cnt[4];
     uint32_t hub = 0;  // bit j: node j is a hub (drawn by the hub kernels)
@@ -949,8 +977,9 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
     if (lane < ZB / 16)
         *reinterpret_cast<uint4 *>(reg + 2 * BUF + 16 * lane) = make_uint4(0, 0, 0, 0);
     const uint32_t *zero = reinterpret_cast<const uint32_t *>(reg + 2 * BUF);
-    const uint32_t rot = (uint32_t)(c + 2) & 31u;
-    // chunk cursor: node j, first record
+    // rotating a mask word right by c + 2 puts chain c's bit at bit 30, the
+    // one set bit of 2.0's high word
+    const uint32_t rot1 = (uint32_t)(c1 + 2) & 31u, rot2 = (uint32_t)(c2 + 2) & 31u;
     auto sel = [&](const uint32_t (&a)[4], int j) -> uint32_t {
         return j == 0 ? a[0] : j == 1 ? a[1] : j == 2 ? a[2] : a[3];
     };
@@ -996,11 +1025,12 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
             if (HB + o < BUF) *reinterpret_cast<uint4 *>(dst + HB + o) = rz[i];
         }
     };
-    const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
-                                   (kPhasePrimal << 30) | (uint32_t)c, t, g.rk);
-    uint32_t drawn = 0;  // byte j: 1 + the new state of node j (0: not drawn)
-    // nodes without records are drawn from their base alone
-    double L[QM];
+    const Words wq1 = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                    (kPhasePrimal << 30) | (uint32_t)c1, t, g.rk);
+    const Words wq2 = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                    (kPhasePrimal << 30) | (uint32_t)c2, t, g.rk);
+    uint32_t drawn1 = 0, drawn2 = 0;  // byte j: 1 + the new state of node j (0: not drawn)
+    double L1[QM], L2[QM];
     int j = 0;
     uint32_t first = 0;
     skip_empty(j, first);
@@ -1009,6 +1039,9 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
     if (jn < 4) issue(jn, fn);
     int b = 0;
     int jdone = 0;  // nodes [0, jdone) are drawn
+    auto word_of = [](const Words &w, int jj) {
+        return (jj == 0 ? w.w0 : jj == 1 ? w.w1 : jj == 2 ? w.w2 : w.w3) >> 8;
+    };
     auto draw_upto = [&](int jend) {  // draw record-less nodes below jend, in order
         for (; jdone < jend; ++jdone) {
             const int64_t node = quad * 4 + jdone;
@@ -1017,8 +1050,8 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
             double Lb[QM];
 #pragma unroll
             for (int a = 0; a < QM; ++a) Lb[a] = (UQ || a < qn) ? g.base[node * QM + a] : 0.0;
-            const uint32_t U = (jdone == 0 ? wq.w0 : jdone == 1 ? wq.w1 : jdone == 2 ? wq.w2 : wq.w3) >> 8;
-            drawn |= (uint32_t)(draw_node<QM, UQ, EXP64>(Lb, qn, U) + 1) << (8 * jdone);
+            drawn1 |= (uint32_t)(draw_node<QM, UQ, EXP64>(Lb, qn, word_of(wq1, jdone)) + 1) << (8 * jdone);
+            drawn2 |= (uint32_t)(draw_node<QM, UQ, EXP64>(Lb, qn, word_of(wq2, jdone)) + 1) << (8 * jdone);
         }
     };
     while (jn < 4) {
@@ -1035,70 +1068,82 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
         const int qn = UQ ? QM : (int)g.q[node];
         if (fc == 0) {
             draw_upto(jc);  // record-less nodes before this one
-            // half 0 starts from the node's base (lam and every c0), half 1 from 0
+            // group 0 starts from the node's base (lam and every c0), the others from 0
 #pragma unroll
-            for (int a = 0; a < QM; ++a)
-                L[a] = (p == 0 && (UQ || a < qn)) ? g.base[node * QM + a] : 0.0;
+            for (int a = 0; a < QM; ++a) {
+                L1[a] = (grp == 0 && (UQ || a < qn)) ? g.base[node * QM + a] : 0.0;
+                L2[a] = L1[a];
+            }
         }
         const double *hs = reinterpret_cast<const double *>(reg + b * BUF + shh);
         const uint32_t *zs = reinterpret_cast<const uint32_t *>(reg + b * BUF + HB + shz);
-        for (uint32_t k = 0; k < nrec; k += 2) {
-            // half p takes record k + p; past the end it reads record k's h
+        for (uint32_t k = 0; k < nrec; k += G) {
+            // group grp takes record k + grp; past the end it reads record k's h
             // with an all-zero mask, which adds nothing
-            const bool has = k + p < nrec;
-            const double *h = hs + (has ? k + p : k) * RP;
-            const uint32_t *z = has ? zs + (k + p) * D : zero;
+            const bool has = k + grp < nrec;
+            const double *h = hs + (has ? k + grp : k) * RP;
+            const uint32_t *z = has ? zs + (k + grp) * D : zero;
 #pragma unroll
             for (int s = 1; s < QM; ++s) {
                 if (!UQ && s >= qn) break;
-                double acc = L[s];
+                double a1 = L1[s], a2 = L2[s];
 #pragma unroll
                 for (int o = 1; o < QM; ++o) {
                     const int dp = (s - 1) * (QM - 1) + (o - 1);
-                    // rotating the word right by c + 2 puts chain c's bit at
-                    // bit 30, the one set bit of 2.0's high word
-                    const uint32_t hi = __builtin_amdgcn_alignbit(z[dp], z[dp], rot) & 0x40000000u;
-                    acc = __builtin_fma(__hiloint2double((int)hi, 0), h[dp], acc);
+                    const uint32_t zw = z[dp];
+                    const double hv = h[dp];
+                    const uint32_t m1 = __builtin_amdgcn_alignbit(zw, zw, rot1) & 0x40000000u;
+                    const uint32_t m2 = __builtin_amdgcn_alignbit(zw, zw, rot2) & 0x40000000u;
+                    a1 = __builtin_fma(__hiloint2double((int)m1, 0), hv, a1);
+                    a2 = __builtin_fma(__hiloint2double((int)m2, 0), hv, a2);
                 }
-                L[s] = acc;
+                L1[s] = a1;
+                L2[s] = a2;
             }
         }
         if (fc + nrec >= sel(cnt, jc)) {
-            // both halves end with the same sum (IEEE addition is commutative)
+            // groups g and g ^ 1, then pairs of groups: every group ends with the
+            // same sums (IEEE addition is commutative)
 #pragma unroll
-            for (int s = 1; s < QM; ++s) L[s] += __shfl_xor(L[s], 32);
-            const uint32_t U = (jc == 0 ? wq.w0 : jc == 1 ? wq.w1 : jc == 2 ? wq.w2 : wq.w3) >> 8;
-            drawn |= (uint32_t)(draw_node<QM, UQ, EXP64>(L, qn, U) + 1) << (8 * jc);
+            for (int s = 1; s < QM; ++s) {
+                L1[s] += __shfl_xor(L1[s], 16);
+                L2[s] += __shfl_xor(L2[s], 16);
+            }
+#pragma unroll
+            for (int s = 1; s < QM; ++s) {
+                L1[s] += __shfl_xor(L1[s], 32);
+                L2[s] += __shfl_xor(L2[s], 32);
+            }
+            drawn1 |= (uint32_t)(draw_node<QM, UQ, EXP64>(L1, qn, word_of(wq1, jc)) + 1) << (8 * jc);
+            drawn2 |= (uint32_t)(draw_node<QM, UQ, EXP64>(L2, qn, word_of(wq2, jc)) + 1) << (8 * jc);
             jdone = jc + 1;
         }
         b ^= 1;
     }
     draw_upto(4);
-    int newx[4];
+    int nx1[4], nx2[4];
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) newx[jj] = (int)((drawn >> (8 * jj)) & 255u) - 1;
+    for (int jj = 0; jj < 4; ++jj) {
+        nx1[jj] = (int)((drawn1 >> (8 * jj)) & 255u) - 1;
+        nx2[jj] = (int)((drawn2 >> (8 * jj)) & 255u) - 1;
+    }
     int qnv[4];  // 0 for nodes this wave does not draw
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
-        qnv[jj] = newx[jj] >= 0 ? (UQ ? QM : (int)g.q[quad * 4 + jj]) : 0;
-    const bool writer = p == 0 && cvalid;
+        qnv[jj] = nx1[jj] >= 0 ? (UQ ? QM : (int)g.q[quad * 4 + jj]) : 0;
+    const bool w1 = grp == 0 && cv1, w2 = grp == 0 && cv2;
     if (count) {
         // the wave owns the quad's counters (one chain block)
-        uint32_t drawn = 0;
+        uint32_t dmask = 0;
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) drawn |= (qnv[jj] > 0 ? 1u : 0u) << jj;
-        count_quad<QM>(g.counts, quad, newx, qnv, drawn, writer, lane);
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int64_t node = quad * 4 + jj;
-            if (newx[jj] >= 0 && writer) g.x[node * g.C + c] = (uint8_t)newx[jj];
-        }
-        return;
+        for (int jj = 0; jj < 4; ++jj) dmask |= (qnv[jj] > 0 ? 1u : 0u) << jj;
+        count_quad2<QM>(g.counts, quad, nx1, nx2, qnv, dmask, w1, w2, lane);
     }
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
         const int64_t node = quad * 4 + jj;
-        if (newx[jj] >= 0 && writer) g.x[node * g.C + c] = (uint8_t)newx[jj];
+        if (nx1[jj] >= 0 && w1) g.x[node * g.C + c1] = (uint8_t)nx1[jj];
+        if (nx2[jj] >= 0 && w2) g.x[node * g.C + c2] = (uint8_t)nx2[jj];
     }
 }
 

@@ -337,3 +337,60 @@ def test_learned_steps_keep_the_marginals():
     z = np.abs(m0 - m1) / np.sqrt(s0 ** 2 + s1 ** 2)
     _say(f"  max |z| {z.max():.2f}")
     assert (z < 4.5).all()
+
+
+def test_full_size_learned_step_sampled():
+    """The learned-proposal workload at full size (512 x 512 binary grid, J ~
+    U(0, 0.35), h ~ N(0, 0.3), 8 x 8 blocks, 128 chains) in the benchmark's
+    launch configuration: one learned step from a state of the plain chain;
+    every cut dual against the oracle, and for 24 sampled blocks (corners and
+    edges included) the proposals, acceptances and new states."""
+    import torch
+    from paper_1611_06684_amd import learned as Lw
+    from paper_1611_06684_amd import pdg_block as pb
+    from paper_1611_06684_amd.pdg import Sampler
+    side, C, seed = 512, 128, 0
+    model = Lw.grid_model(side, seed=0)
+    s = Sampler(model, C, seed=seed)
+    s.init()
+    s.sweep(20)
+    bp = pb.BlockProposal(s, model, side, side, init_seed=0)
+    x = s.state().cpu().numpy()
+    rows = bp.rows
+    prop = torch.zeros((rows, 64), dtype=torch.uint8, device=s.dev)
+    acc = torch.zeros(rows, dtype=torch.uint8, device=s.dev)
+    flag = torch.zeros(rows, dtype=torch.uint8, device=s.dev)
+    bp.step(prop=prop, acc=acc, flag=flag)
+    th_g = torch.zeros((model.m, C), dtype=torch.uint8, device=s.dev)
+    pb.pdg_blk_get_cut_duals(bp.blk, th_g.data_ptr(), s.ctx)
+    th_g = th_g.cpu().numpy()
+    x_g = s.state().cpu().numpy()
+    lg = bp.logits.cpu().numpy()
+    prop = prop.cpu().numpy()
+    acc = acc.cpu().numpy().astype(bool)
+    fl_g = flag.cpu().numpy().astype(bool)
+    bp.close()
+    s.close()
+    blk = B.Blocking(side, side, 8)
+    dec = oracle.decompose(model)
+    th_o, dfl = B.cut_duals(model, dec, blk, x, seed, 1)
+    assert ((th_g != th_o) & (dfl == 0)).sum() == 0
+    n_dflag = int(dfl[blk.cut].sum())
+    _say(f"  cut duals: {int(blk.cut.sum()) * C} draws, flagged {n_dflag}")
+    assert n_dflag <= max(1e-5 * blk.cut.sum() * C, 3)
+    f_o, internal = B.block_fields(model, dec, blk, th_g)
+    K = B.block_couplings(blk, internal)
+    rng = np.random.default_rng(3)
+    blocks = np.unique(np.concatenate([[0, 63, 4032, 4095, 64, 127], rng.choice(blk.nb, 18,
+                                                                                replace=False)]))
+    lgb = lg.reshape(blk.nb, C, 64)[blocks]
+    x_o, acc_o, fl_o, xp_o = B.mh_step(blk, x, f_o[blocks], K[blocks], lgb, seed, 1, blocks=blocks)
+    fl_gb = fl_g.reshape(blk.nb, C)[blocks]
+    assert np.array_equal(fl_gb, fl_o)
+    ok = ~fl_o
+    assert np.array_equal(prop.reshape(blk.nb, C, 64)[blocks][ok], xp_o[ok])
+    assert np.array_equal(acc.reshape(blk.nb, C)[blocks][ok], acc_o[ok])
+    for j, b in enumerate(blocks):
+        for c in np.flatnonzero(ok[j]):
+            assert np.array_equal(x_g[blk.nodes[b], c], x_o[blk.nodes[b], c]), (b, c)
+    _say(f"  {len(blocks)} blocks x {C} chains: accepted {int(acc_o.sum())}, flagged {int(fl_o.sum())}")

@@ -837,31 +837,41 @@ def test_full_size_dynamic_sparse_sampled():
 
 
 def test_full_size_batched_by_states_sampled():
-    """Batched workload at full size (512 graphs: 504 sparse with q in {2,3,5}, 8
-    dense binary on 2048 nodes; FP32 tables; 8 chains) in the layout the
-    benchmark times by default: one context per state count, distinct generator
-    seeds.  In each context: two sweeps from init, then one sweep whose sampled
-    nodes -- two nodes of dense graphs in the binary context, 2047 incidences
-    each -- and all their incident edges are checked one by one by the oracle."""
+    """Batched workload at its full recipe (4096 graphs: sparse with q in
+    {2,3,5}, 64 dense binary graphs on 2048 nodes; FP32 tables; 8 chains) in
+    the configuration the benchmark times: one context per state count, each
+    tuned by pdg_tune, sweeps replayed from one captured HIP graph.  After two
+    replays, the draws of a third are checked on sampled nodes (two of them in
+    dense graphs, 2047 incidences each) and all their incident edges, one by
+    one, against the oracle."""
     import torch
+    from paper_1611_06684_amd import pdg
     C = 8
-    _say("[batched full-size] building the batch")
-    batch = W.batched_uneven(512, 8, seed=0)
-    groups = W.group_by_states(batch)
-    del batch
-    rng = np.random.default_rng(0)
+    _say("[batched full-size] building the batch per state count")
+    groups = W.batched_by_states(4096, 64, seed=0)
+    samplers = []
     for k, (q, model) in enumerate(groups):
-        seed = k
-        _say(f"[batched full-size] q={q}: n={model.n} m={model.m}, seed {seed}")
-        s = _sampler(model, C, seed)
+        _say(f"[batched full-size] q={q}: n={model.n} m={model.m}, seed {k}")
+        s = _sampler(model, C, k)
         s.init()
-        s.sweep(2)
-        x_prev = s.state().cpu().numpy()
-        s.dual_phase()
+        tun = pdg.pdg_tune(s.ctx, 2)
+        _say(f"  tuning {tun.as_dict()}")
+        samplers.append(s)
+    graph = pdg.pdg_graph_create([s.ctx for s in samplers], 1)
+    pdg.pdg_graph_launch(graph)
+    pdg.pdg_graph_launch(graph)
+    x_prev = [s.state().cpu().numpy() for s in samplers]
+    pdg.pdg_graph_launch(graph)
+    pdg.pdg_graph_destroy(graph)
+    rng = np.random.default_rng(0)
+    for k, ((q, model), s) in enumerate(zip(groups, samplers)):
+        seed = k
+        t = s.t
+        assert t == 3
         uids = _u64(s.uids)
         nodes = rng.choice(model.n, size=60, replace=False)
-        if q == 2:  # graphs 0..7 are the dense ones and come first
-            nodes = np.unique(np.concatenate([nodes, [5, 2048 * 7 + 100]]))
+        if q == 2:  # the dense graphs come first in the binary context
+            nodes = np.unique(np.concatenate([nodes, [5, 2048 * 63 + 100]]))
         ends = np.concatenate([model.src, model.dst])
         order = np.argsort(ends, kind="stable")
         se = ends[order]
@@ -869,17 +879,16 @@ def test_full_size_batched_by_states_sampled():
         inc = {int(i): order[a:b] for i, a, b in zip(nodes, lo, hi)}
         edges = np.unique(np.concatenate(list(inc.values())) % model.m)
         th_g = _u64(s.duals(torch.as_tensor(uids[edges].view(np.int64), device=s.dev)))
-        s.primal_phase()
         x_new = s.state().cpu().numpy()
-        t = s.t
         subm = model.subset_edges(edges)
         dec = oracle.decompose(subm)
         sub = {int(e): j for j, e in enumerate(edges)}
         n_draw = n_flag = 0
+        xp = x_prev[k]
         for j, e in enumerate(edges):
             for c in range(C):
-                th, fl = oracle.dual_edge(subm, dec, j, x_prev[model.src[e], c],
-                                          x_prev[model.dst[e], c], uids[e], c, t, seed)
+                th, fl = oracle.dual_edge(subm, dec, j, xp[model.src[e], c], xp[model.dst[e], c],
+                                          uids[e], c, t, seed)
                 assert ((int(th_g[j, c]) ^ th) & ~fl) == 0, (q, e, c)
                 n_draw += (q - 1) * (q - 1)
                 n_flag += bin(fl).count("1")
@@ -896,5 +905,5 @@ def test_full_size_batched_by_states_sampled():
         _say(f"  q={q}: {len(nodes)} nodes, {len(edges)} edges, sampled draws {n_draw}, "
              f"flagged {n_flag}")
         assert n_flag <= max(FLAG_BUDGET * n_draw, 3)
+    for s in samplers:
         s.close()
-        del s
