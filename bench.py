@@ -1,7 +1,7 @@
 """Benchmark of the primal-dual Gibbs sweep on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--workload dynamic-sparse|plain-grid|tiny|batched]
+                    [--workload dynamic-sparse|plain-grid|tiny|batched|learned]
 
 Workloads (seeded, synthetic; recipes in workloads.py):
   dynamic-sparse (default, the headline line: the largest single-GPU
@@ -15,11 +15,17 @@ Workloads (seeded, synthetic; recipes in workloads.py):
   tiny: 4 x 4 binary grid (Ising tables exp(J s s'), J ~ U(-0.3, 0.3), unaries
     exp(h s), h ~ N(0, 0.5)), FP64, one chain: bound by latency, so its line is
     sweeps/s (steps = sweeps, run in batches of one launch each).
-  batched: 512 independent graphs: 504 sparse graphs with N ~ logU[100, 50000],
-    mean degree U{3..12}, q ~ U{2,3,5}, plus 8 dense binary graphs on 2048 nodes;
-    8 chains.  By default one context per state count (one launch per phase for
-    all graphs with that count); --batch-layout one puts the whole batch in one
-    context.
+  batched: 4096 independent graphs: 4032 sparse graphs with N ~ logU[100, 50000],
+    mean degree U{3..12}, q ~ U{2,3,5}, plus 64 complete binary graphs on 2048
+    nodes (Ising tables, J ~ N(0, 0.5 / sqrt(2048))); 8 chains.  Built directly
+    as one context per state count, each tuned by pdg_tune; the timed sweeps
+    are replays of one captured HIP graph of --graph-sweeps sweeps of every
+    context.  After the timed region, the dense graphs' gather is timed in its
+    vector and FP64 matrix-core forms (config.dense_gather).
+  learned: the learned block proposal on a 512 x 512 binary grid (8 x 8
+    blocks, 128 chains): the proposal network is trained on plain-sampler
+    block states, then ESS/s of (learned step + plain sweep) is compared with
+    plain sweeps at equal marginal error; steps = iterations.
 A step is one full sweep: the dual phase over every edge and chain, then the
 primal phase over every node and chain (with marginal counting).  The metric is
 chain * (|V| + |E|) updates/s with every input resident in HBM.
@@ -468,6 +474,43 @@ class SamplerGroup:
             s.primal_phase()
 
 
+FP64_PEAK = 78.6e12
+
+
+def dense_gather_experiment(sampler, nodes, n_dense, C, stream, reps=20):
+    """The dense graphs' gather two ways, outside the timed sweeps: the field of
+    state 1 of every node of the complete binary graphs (the first `nodes` nodes
+    of the binary context, 2047 incidences each) given the current duals, by
+    vector FMAs and by FP64 matrix-core products (pdg_dense_fields).  The
+    matrix-core form issues one 16x16x4 product per 4 records of a node, of
+    which one column of 16 is used."""
+    import torch
+    from paper_1611_06684_amd import pdg_block as pb
+    ids = torch.arange(nodes, dtype=torch.int32, device=sampler.dev)
+    out = torch.empty((nodes, C), dtype=torch.float64, device=sampler.dev)
+    sampler.dual_phase()
+    ms = {}
+    for method, name in ((0, "valu"), (1, "mfma")):
+        for _ in range(3):
+            pb.pdg_dense_fields(sampler.ctx, nodes, ids.data_ptr(), method, out.data_ptr())
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            pb.pdg_dense_fields(sampler.ctx, nodes, ids.data_ptr(), method, out.data_ptr())
+        b.record(stream)
+        b.synchronize()
+        ms[name] = a.elapsed_time(b) / reps
+    sampler.primal_phase()
+    recs = n_dense - 1
+    useful = 2.0 * nodes * recs * C
+    issued = nodes * ((recs + 3) // 4) * (16 * 16 * 4 * 2)
+    return {"nodes": nodes, "records_per_node": recs, "chains": C,
+            "valu_ms": ms["valu"], "mfma_ms": ms["mfma"],
+            "useful_gflop": useful / 1e9, "mfma_issued_gflop": issued / 1e9,
+            "mfma_issued_frac_of_fp64_peak": issued / (ms["mfma"] / 1e3) / FP64_PEAK,
+            "faster": "valu" if ms["valu"] <= ms["mfma"] else "mfma"}
+
+
 def run_batched(args):
     """The batched workload at its full recipe: 4096 independent graphs (64 of
     them complete binary graphs on 2048 nodes), one context per state count,
@@ -521,6 +564,7 @@ def run_batched(args):
     wall = time.perf_counter() - wall0
     total_ms = a.elapsed_time(b)
     pdg.pdg_graph_destroy(graph)
+    dense = dense_gather_experiment(samplers[0], n_dense * 2048, 2048, C, stream)
     for s in samplers:
         s.sync()
         s.close()
@@ -539,6 +583,7 @@ def run_batched(args):
                    "contexts": [{"q": q, "nodes": n, "edges": m} for q, n, m in sizes],
                    "nodes": n_nodes, "edges": n_edges, "chains": C, "seed": seed,
                    "tuning": tuning, "dual_ms_eager": dual_ms, "primal_ms_eager": primal_ms,
+                   "dense_gather": dense,
                    "wall_s": wall, "kernel_sources": kernel_digest()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

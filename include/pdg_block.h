@@ -130,6 +130,18 @@ pdg_status pdg_mlp_adam(float *d_w, const float *d_g, float *d_m, float *d_v, in
                         float lr, float beta1, float beta2, float eps, uint16_t *d_wbf,
                         void *stream);
 
+/* The dense gather on the matrix cores (an experiment).  In a binary context
+ * (q_max 2) with at most 16 chains, between the two phases of a sweep, writes
+ * each listed node's field of state 1 given the current duals,
+ * base_i(1) + sum_r 2 theta_r^c h_r over its incidence records, to d_out:
+ * double [n][C].  method 0: vector FMAs (the hub kernels' arithmetic); method
+ * 1: v_mfma_f64_16x16x4_f64 with the duals as a 16-chain x 4-record 0/1 matrix
+ * and 2h in one column of 16 (a batched matrix-vector product: no operand is
+ * shared between nodes).  Both FP64, results equal up to summation order.
+ * d_nodes: int32 [n] node ids. */
+pdg_status pdg_dense_fields(pdg_ctx *ctx, int64_t n, const int32_t *d_nodes, int32_t method,
+                            double *d_out);
+
 #ifdef __cplusplus
 }
 #endif

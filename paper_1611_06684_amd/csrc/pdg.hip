@@ -192,7 +192,9 @@ pdg_status ctx_view(pdg_ctx *ctx, CtxView *v)
     PDG_TRY(set_dev(ctx));
     *v = CtxView{ctx->device, ctx->stream, ctx->d_x,          ctx->d_q,
                  ctx->n,      ctx->C,      ctx->QM,           ctx->cfg.precision,
-                 ctx->cfg.seed, ctx->phase};
+                 ctx->cfg.seed, ctx->phase, ctx->d_rec_p,      ctx->d_rec_z,
+                 ctx->d_off,  ctx->d_cnt,  ctx->d_base,       ctx->RP,
+                 ctx->ZW};
     return PDG_OK;
 }
 

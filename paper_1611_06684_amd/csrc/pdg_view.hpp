@@ -20,6 +20,14 @@ struct CtxView {
     int32_t C, QM, precision;
     uint64_t seed;
     int phase;  // 0 between sweeps, 1 between the dual and the primal phase
+    // incidence records (each node's segment [off, off + cnt) of the pool):
+    // h [pool][RP] in the node's orientation, dual mask words [pool][ZW]
+    const double *rec_p;
+    const uint32_t *rec_z;
+    const uint32_t *inc_off, *inc_cnt;
+    const double *base;  // [n][QM] log unaries plus the records' theta-free fields
+    int32_t RP;
+    int64_t ZW;
 };
 
 // Fills *v and makes the context's device current; a failure (a broken

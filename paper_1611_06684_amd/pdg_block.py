@@ -25,7 +25,8 @@ MLP_PARAMS = 107072
 
 EXPORTS = ["pdg_blk_create", "pdg_blk_destroy", "pdg_blk_cut_duals", "pdg_blk_inputs",
            "pdg_blk_mh", "pdg_blk_get_cut_duals", "pdg_blk_info", "pdg_blk_set_step",
-           "pdg_mlp_forward", "pdg_mlp_backward_workspace", "pdg_mlp_backward", "pdg_mlp_adam"]
+           "pdg_mlp_forward", "pdg_mlp_backward_workspace", "pdg_mlp_backward", "pdg_mlp_adam",
+           "pdg_dense_fields"]
 
 _SIG = {
     "pdg_blk_create": [_P, _I32, _I32, _P, _P, ctypes.POINTER(_P)],
@@ -40,6 +41,7 @@ _SIG = {
     "pdg_mlp_backward_workspace": [_I64, ctypes.POINTER(_I64)],
     "pdg_mlp_backward": [_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P],
     "pdg_mlp_adam": [_P, _P, _P, _P, _I64, _F32, _F32, _F32, _F32, _P, _P],
+    "pdg_dense_fields": [_P, _I64, _P, _I32, _P],
 }
 _declared = False
 
@@ -116,6 +118,10 @@ def pdg_mlp_backward(d_wbf, rows, d_in, d_h1, d_h2, d_logits, d_target, d_grad, 
 
 def pdg_mlp_adam(d_w, d_g, d_m, d_v, step, lr, beta1, beta2, eps, d_wbf, stream=0):
     _chk(_lib().pdg_mlp_adam(d_w, d_g, d_m, d_v, step, lr, beta1, beta2, eps, d_wbf, stream))
+
+
+def pdg_dense_fields(ctx, n, d_nodes, method, d_out):
+    _chk(_lib().pdg_dense_fields(ctx, n, d_nodes, method, d_out), ctx)
 
 
 def bf16_bits(a: np.ndarray) -> np.ndarray:
