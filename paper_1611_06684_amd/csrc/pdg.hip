@@ -294,8 +294,11 @@ static void launch_primal_t(const Graph &g, uint32_t t, int count, int CB, hipSt
         const int64_t waves = cdiv(g.n, 4) * CB;
         k_primal64<QM, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
     } else if constexpr (LPI == 32) {
-        const int64_t waves = cdiv(g.n, 4);  // one quad per wave, halves split the records
-        k_primal32<QM, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
+        const int64_t waves = cdiv(g.n, 4);  // one quad per wave, record groups split the records
+        if constexpr (QM >= 6)  // chain-major dual words (zc_layout)
+            k_primal32z<QM, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
+        else
+            k_primal32<QM, UQ, E64><<<grid_for(waves * 64), 256, 0, s>>>(g, t, count);
     } else if constexpr ((LPI == 8 || LPI == 16) && QM >= 3) {
         // records of 4 or more entries: staged once per wave (binary records
         // are one word and one double; there the plain form is as fast)
@@ -359,8 +362,12 @@ static void hubs_t(pdg_ctx *ctx, const Graph &g, uint32_t t, int count, int64_t 
                    const uint32_t *hn, const uint32_t *hp, const uint32_t *pnode,
                    const uint32_t *pf, const uint32_t *pn)
 {
-    k_hub_pieces<QM, LPI><<<grid_for(wp * 64), 256, 0, ctx->stream>>>(g, ctx->np, pnode, pf, pn,
-                                                                      ctx->d_part);
+    if constexpr (LPI == 32 && QM >= 6)
+        k_hub_pieces_z<QM><<<grid_for(wp * 64), 256, 0, ctx->stream>>>(g, ctx->np, pnode, pf, pn,
+                                                                        ctx->d_part);
+    else
+        k_hub_pieces<QM, LPI><<<grid_for(wp * 64), 256, 0, ctx->stream>>>(g, ctx->np, pnode, pf, pn,
+                                                                          ctx->d_part);
     k_hub_finish<QM, UQ, E64, LPI><<<grid_for(wf * 64), 256, 0, ctx->stream>>>(
         g, ctx->nh, hn, hp, ctx->d_part, t, count);
 }
@@ -728,7 +735,7 @@ static pdg_status rebuild_hubs(pdg_ctx *ctx, uint32_t *flag, uint32_t *pieces, u
     const int64_t D = ctx->D, RP = ctx->RP;
     const int64_t zr = ctx->LPI == 64 ? 2 * D * ctx->CB : D;
     const int64_t zb = (8 * D + 15) / 16 * 16;
-    const int64_t K = (4096 - zb - 48) / (RP * 8 + 4 * zr);
+    const int64_t K = zc_layout(ctx->QM, ctx->C) ? kZChunk : (4096 - zb - 48) / (RP * 8 + 4 * zr);
     if (K < (ctx->LPI == 64 ? 1 : 64 / ctx->LPI) || ctx->tune_hub_thr == 0) return PDG_OK;
     const int64_t n = ctx->n;
     const hipStream_t st = ctx->stream;

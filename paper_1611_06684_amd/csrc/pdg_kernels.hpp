@@ -30,7 +30,11 @@
 //                                         same entry order: with C <= 32 a
 //                                         32-bit word per (record, entry), bit
 //                                         c; with C > 32 a 64-bit word per
-//                                         (record, block of 64 chains, entry)
+//                                         (record, block of 64 chains, entry).
+//                                         With 17..32 chains and q_max >= 6
+//                                         chain-major instead: [pool][C] 64-bit
+//                                         words, bit 8 (r-1) + (o-1) of chain
+//                                         c's word (zc_layout)
 //   ipos    uint32 [slot][2]              record index of the src / dst side
 //   counts  uint32 [n][QM]                marginal counters
 // Parameter block of an edge (QM = q_max, D = (QM-1)^2, entry d = (a-1)(q_dst-1)+(b-1)):
@@ -113,10 +117,29 @@ __device__ __forceinline__ void sweep_args(const Graph &g, uint32_t &t)
 }
 
 __host__ __device__ constexpr int rec_len(int qm) { return dim_d(qm); }
+// Chain-major dual words: with 17..32 chains and records of 25 or more
+// entries a record keeps one 64-bit word per chain (own state r in byte r-1,
+// other state o in bit o-1 of it), so the primal reads a chain's duals of a
+// whole record with one load and sums them through subset-sum tables
+// (k_primal32z); otherwise one mask word per entry with a bit per chain.
+__host__ __device__ constexpr bool zc_layout(int qm, int C) { return qm >= 6 && C >= 17 && C <= 32; }
 // u32 words of dual masks per incidence record
 __host__ __device__ inline int64_t rec_words(int qm, int C)
 {
+    if (zc_layout(qm, C)) return 2 * (int64_t)C;
     return C <= 32 ? (int64_t)dim_d(qm) : 2 * (int64_t)((C + 63) / 64) * dim_d(qm);
+}
+// Dual bit of chain c for padded entry dp (own state dp / (QM-1) + 1, other
+// dp % (QM-1) + 1) of record r, in either layout.
+__device__ __forceinline__ uint32_t rec_theta(const Graph &g, uint64_t r, int dp, int c, int qm)
+{
+    if (zc_layout(qm, g.C)) {
+        const uint64_t w = reinterpret_cast<const uint64_t *>(g.rec_z)[r * (uint64_t)g.C + c];
+        return (uint32_t)(w >> (8 * (dp / (qm - 1)) + dp % (qm - 1))) & 1u;
+    }
+    const int D = dim_d(qm);
+    const uint64_t i = g.C <= 32 ? r * D + dp : ((r * g.CB + (c >> 6)) * D + dp) * 2 + ((c >> 5) & 1);
+    return (g.rec_z[i] >> (c & 31)) & 1u;
 }
 
 // u32 index of the mask word holding chain c of padded entry dp of record r.
@@ -326,7 +349,10 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
     // items are gathered into lanes p D + d and stored record by record (one
     // contiguous run per record); otherwise the first lane of each item
     // stores its words, with the record addresses loaded before the draws
-    constexpr bool GATHER = LPI >= 32 || (LPI >= 8 && D >= 4);
+    // ZC (17..32 chains, q_max >= 6): each lane keeps its chain's words of
+    // both records (chain-major layout) and stores them at the end
+    constexpr bool ZC = LPI == 32 && QM >= 6;
+    constexpr bool GATHER = !ZC && (LPI >= 32 || (LPI >= 8 && D >= 4));
     constexpr int NW = GATHER ? P * D : 1;
     constexpr int NREG = (NW + 63) / 64;
     constexpr uint32_t WMASK = LPI >= 32 ? 0xFFFFFFFFu : (1u << LPI) - 1u;
@@ -353,6 +379,16 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
     const int De = UQ ? D : (qs - 1) * (qd - 1);
     const uint32_t ulo = (uint32_t)uid, uhi = (uint32_t)(uid >> 32);
     const uint64_t mact = __ballot(active);
+    // with two items per wave their sign words are taken to scalar registers,
+    // so the per-entry sign mask is scalar work
+    uint32_t sg[2][2] = {{0u, 0u}, {0u, 0u}};  // [item][word]
+    if constexpr (LPI == 32) {
+        const uint32_t slo = (uint32_t)sign, shi = (uint32_t)(sign >> 32);
+        sg[0][0] = __builtin_amdgcn_readlane(slo, 0);
+        sg[0][1] = __builtin_amdgcn_readlane(shi, 0);
+        sg[1][0] = __builtin_amdgcn_readlane(slo, 32);
+        sg[1][1] = __builtin_amdgcn_readlane(shi, 32);
+    }
     // lane masks of the one-hot bits y = [x_src = a], y' = [x_dst = b]
     uint64_t mya[QM], myb[QM];
 #pragma unroll
@@ -363,7 +399,8 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
     uint32_t outr[NREG];
 #pragma unroll
     for (int r = 0; r < NREG; ++r) outr[r] = 0u;
-    const bool leader = live && (lm.lane % LPI == 0);
+    uint32_t zs[2] = {0u, 0u}, zd[2] = {0u, 0u};  // ZC: src and dst record words of this chain
+    const bool leader = !ZC && live && (lm.lane % LPI == 0);
     // records of the two endpoints receive the masks
     const uint64_t r0 = live ? g.ipos[2 * sl] : 0ull, r1 = live ? g.ipos[2 * sl + 1] : 0ull;
     int a = 1, b = 1;
@@ -385,7 +422,14 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
             // Lanes of absent chains produce bits that nothing reads.
             const uint64_t ya = UQ ? mya[dd / (QM - 1) + 1] : __ballot(xs == a);
             const uint64_t yb = UQ ? myb[dd % (QM - 1) + 1] : __ballot(xd == b);
-            const uint64_t neg = __ballot(((sign >> dd) & 1ull) != 0);
+            uint64_t neg;
+            if constexpr (LPI == 32) {
+                const uint32_t n0 = 0u - ((sg[0][dd >> 5] >> (dd & 31)) & 1u);
+                const uint32_t n1 = 0u - ((sg[1][dd >> 5] >> (dd & 31)) & 1u);
+                neg = ((uint64_t)n1 << 32) | n0;
+            } else {
+                neg = __ballot(((sign >> dd) & 1ull) != 0);
+            }
             const uint64_t yh = ya ^ neg;
             const uint32_t tp8m1 = thr[2 * dd], tm8 = thr[2 * dd + 1];
             const uint64_t cp = __ballot(W[j] > tp8m1);          // U >= T+
@@ -393,7 +437,24 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
             const uint64_t ch = __ballot(W[j] >= 0x80000000u);   // U >= 2^23
             uint64_t zm = cp | (ch & (yh | yb)) | (cm & yh & yb);
             if (!UQ) zm &= __ballot(dd < De) & mact;
-            if (GATHER) {
+            if constexpr (ZC) {
+                // bit 8 (a-1) + (b-1) of the src word, 8 (b-1) + (a-1) of the dst word
+                const int ai = UQ ? dd / (QM - 1) : a - 1, bi = UQ ? dd % (QM - 1) : b - 1;
+                const uint32_t th = lane_bit(zm) ? 1u : 0u;
+                const int ps = 8 * ai + bi, pd = 8 * bi + ai;
+                if (UQ) {
+                    zs[ps >> 5] |= th << (ps & 31);
+                    zd[pd >> 5] |= th << (pd & 31);
+                } else {
+                    // entries past the edge's own carry th = 0
+                    const uint32_t vs = th << (ps & 31), vd = th << (pd & 31);
+                    zs[0] |= ps < 32 ? vs : 0u;
+                    zs[1] |= ps < 32 ? 0u : vs;
+                    zd[0] |= pd < 32 ? vd : 0u;
+                    zd[1] |= pd < 32 ? 0u : vd;
+                }
+
+            } else if (GATHER) {
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
                     const int idx = p * D + dd;
@@ -414,11 +475,29 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
                 }
             }
         }
+        // ZC: fold each call's bits into the words here (left alone, the
+        // compiler defers every select to the end, and the compare masks of
+        // all entries, held until then, exceed the scalar registers)
+        if constexpr (ZC) {
+            // (an identity DPP move: opaque to the compiler, costs one VALU)
+            zs[0] = __builtin_amdgcn_mov_dpp((int)zs[0], 0xE4, 0xF, 0xF, false);
+            zs[1] = __builtin_amdgcn_mov_dpp((int)zs[1], 0xE4, 0xF, 0xF, false);
+            zd[0] = __builtin_amdgcn_mov_dpp((int)zd[0], 0xE4, 0xF, 0xF, false);
+            zd[1] = __builtin_amdgcn_mov_dpp((int)zd[1], 0xE4, 0xF, 0xF, false);
+        }
     }
     // GATHER: the gathered mask words go out to both records, each in its
     // node's orientation: (a-1)(QM-1) + (b-1) in the src record, (b-1)(QM-1) +
     // (a-1) in the dst record; lane p D + d of register r (index 64 r + lane)
     // holds item p's word of entry d, so consecutive lanes fill one record.
+    if constexpr (ZC) {
+        if (active) {
+            uint2 *z = reinterpret_cast<uint2 *>(g.rec_z);
+            z[r0 * (uint64_t)g.C + lm.c] = make_uint2(zs[0], zs[1]);
+            z[r1 * (uint64_t)g.C + lm.c] = make_uint2(zd[0], zd[1]);
+        }
+        return;
+    }
     auto padded = [&](int dd, int qdv) -> int {
         return (dd / (qdv - 1)) * (QM - 1) + dd % (qdv - 1);
     };
@@ -1148,6 +1227,209 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
 }
 
 // ---------------------------------------------------------------------------
+// Subset-sum tables of a record (chain-major dual words, zc_layout).  For own
+// state r the field adds sum_o 2 theta_o h_ro over the other end's states o =
+// 1..QM-1; byte r-1 of a chain's word holds those theta_o as bits o-1.  Per
+// (record, r) the 16 sums over every subset of o = 1..4 (low nibble) and the
+// 8 over o = 5..7 (bits 4..6) are tabulated once per wave, so a chain adds
+// its field of state r with two table reads instead of QM-1 tests and FMAs.
+// Table pair of (record k, own state r): 24 doubles at (k (QM-1) + r-1) 24.
+// ---------------------------------------------------------------------------
+constexpr int kZChunk = 4;  // records per step of the chain-major hub pieces
+constexpr int kZPair = 24;  // doubles per (record, own state) table pair
+
+// One table pair from the 2 h of o = 1..QM-1 (entries past QM-1 zero):
+// lo[m] = sum of the o = i+1 with bit i of m, i < 4; hi[m] likewise for o = i+5.
+template <int QM>
+__device__ __forceinline__ void build_tables(const double (&h)[QM - 1], double *__restrict__ dst)
+{
+    constexpr int S = QM - 1;
+    const double a1 = 2.0 * h[0], a2 = 2.0 * h[1], a3 = 2.0 * h[2], a4 = 2.0 * h[3];
+    const double b1 = S >= 5 ? 2.0 * h[S >= 5 ? 4 : 0] : 0.0;
+    const double b2 = S >= 6 ? 2.0 * h[S >= 6 ? 5 : 0] : 0.0;
+    const double b3 = S >= 7 ? 2.0 * h[S >= 7 ? 6 : 0] : 0.0;
+    double T[24];
+    T[0] = 0.0;
+    T[1] = a1;
+    T[2] = a2;
+    T[3] = a2 + a1;
+    T[4] = a3;
+    T[5] = a3 + a1;
+    T[6] = a3 + a2;
+    T[7] = a3 + T[3];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) T[8 + m] = m == 0 ? a4 : a4 + T[m];
+    T[16] = 0.0;
+    T[17] = b1;
+    T[18] = b2;
+    T[19] = b2 + b1;
+    T[20] = b3;
+    T[21] = b3 + b1;
+    T[22] = b3 + b2;
+    T[23] = b3 + T[19];
+    double2 *d2 = reinterpret_cast<double2 *>(dst);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) d2[i] = make_double2(T[2 * i], T[2 * i + 1]);
+}
+
+// Adds a chain's field of every own state r >= 1 of one record: L[r] += lo + hi
+// of the table pair of (record, r) at the byte r-1 of its word w.
+template <int QM>
+__device__ __forceinline__ void add_tables(const double *__restrict__ tk, uint64_t w, double (&L)[QM])
+{
+    const uint32_t wl = (uint32_t)w, wh = (uint32_t)(w >> 32);
+#pragma unroll
+    for (int r = 1; r < QM; ++r) {
+        const uint32_t src = r <= 4 ? wl : wh;
+        const uint32_t sh = (uint32_t)(8 * ((r - 1) & 3));
+        const uint32_t lo = __builtin_amdgcn_ubfe(src, sh, 4u), hi = __builtin_amdgcn_ubfe(src, sh + 4u, 3u);
+        const double *t = tk + (r - 1) * kZPair;
+        double a = L[r] + t[lo];
+        L[r] = a + t[16 + hi];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a4 + a5 with 17..32 chains and q_max >= 6 (chain-major dual words): one
+// node quad per wave, record group g = lane / 16 (chains l and l + 16 of
+// lane l of the group) takes node 4 Q + g and walks its records, one per
+// step, so a step takes up to four records, one per group.  A step's table
+// pairs are built into the wave's LDS region by the first 4 (QM-1) lanes
+// (lane (QM-1) g + r - 1 builds the pair of own state r of group g's record
+// from the h row it loaded) and read back by the group's lanes.  Loads run
+// through two register buffers, so while one step is processed the next two
+// are in flight.  No cross-group sum is needed and the four nodes are drawn
+// at once; a wave takes as many steps as its busiest node has records.
+// ---------------------------------------------------------------------------
+template <int QM, bool UQ, bool EXP64>
+__global__ __launch_bounds__(256) void k_primal32z(Graph g, uint32_t t, int count)
+{
+    sweep_args(g, t, count);
+    constexpr int D = dim_d(QM);
+    constexpr int S = QM - 1;
+    constexpr int G = 4;
+    static_assert(G * S <= 64, "one table pair per lane");
+    __shared__ __align__(16) double tab[4][G * S * kZPair];
+    const int lane = threadIdx.x & 63;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t quad = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    const int grp = lane >> 4;
+    const int c1 = lane & 15, c2 = c1 + 16;
+    const bool cv1 = c1 < g.C, cv2 = c2 < g.C;
+    if (quad * 4 >= g.n) return;
+    // this group's node, and the table-building lane's node
+    const int64_t node = quad * 4 + grp;
+    const bool nin = node < g.n;
+    const int kb = lane / S, rb = lane % S;  // builder: group kb, own state rb + 1
+    const bool bl = lane < G * S;
+    uint32_t cnt_g = 0, off_g = 0, cnt_b = 0, off_b = 0;
+    bool hub_g = false;
+    {
+        uint32_t cnt[4], off[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            off[j] = g.inc_off[quad * 4 + j];
+            cnt[j] = quad * 4 + j < g.n ? g.inc_cnt[quad * 4 + j] : 0u;
+            if (g.heavy && cnt[j] > g.heavy) {
+                if (j == grp) hub_g = true;
+                cnt[j] = 0;
+            }
+        }
+        cnt_g = grp == 0 ? cnt[0] : grp == 1 ? cnt[1] : grp == 2 ? cnt[2] : cnt[3];
+        off_g = grp == 0 ? off[0] : grp == 1 ? off[1] : grp == 2 ? off[2] : off[3];
+        cnt_b = kb == 0 ? cnt[0] : kb == 1 ? cnt[1] : kb == 2 ? cnt[2] : kb == 3 ? cnt[3] : 0u;
+        off_b = kb == 0 ? off[0] : kb == 1 ? off[1] : kb == 2 ? off[2] : kb == 3 ? off[3] : 0u;
+    }
+    // steps of the wave: the largest record count of its nodes
+    uint32_t nsteps = cnt_g;
+#pragma unroll
+    for (int o = 16; o < 64; o <<= 1) nsteps = max(nsteps, (uint32_t)__shfl_xor((int)nsteps, o));
+    nsteps = __builtin_amdgcn_readfirstlane(nsteps);
+    double *tw = tab[wib];
+    const uint64_t *z64 = reinterpret_cast<const uint64_t *>(g.rec_z);
+    const uint64_t C = (uint64_t)g.C;
+    auto issue = [&](uint32_t st, double (&h)[S], uint64_t &w1, uint64_t &w2) {
+        const bool hb = bl && st < cnt_b;
+        const double *hp = g.rec_p + ((uint64_t)off_b + st) * D + rb * S;
+#pragma unroll
+        for (int o = 0; o < S; ++o) h[o] = hb ? hp[o] : 0.0;
+        const bool has = st < cnt_g;
+        const uint64_t r = (uint64_t)off_g + st;
+        w1 = has && cv1 ? z64[r * C + c1] : 0ull;
+        w2 = has && cv2 ? z64[r * C + c2] : 0ull;
+    };
+    const int qn = UQ ? QM : (nin ? (int)g.q[node] : QM);
+    double L1[QM], L2[QM];
+#pragma unroll
+    for (int a = 0; a < QM; ++a) {
+        L1[a] = (nin && (UQ || a < qn)) ? g.base[node * QM + a] : 0.0;
+        L2[a] = L1[a];
+    }
+    auto process = [&](uint32_t st, const double (&hc)[S], uint64_t wc1, uint64_t wc2) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (bl && st < cnt_b) build_tables<QM>(hc, tw + (kb * S + rb) * kZPair);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // a group whose node has no record at this step reads its table pair
+        // at index 0 (0.0): its word is 0; those tables were built at step 0
+        // or hold zeros written below
+        const double *tk = tw + grp * (S * kZPair);
+        add_tables<QM>(tk, wc1, L1);
+        asm volatile("" ::: "memory");
+        add_tables<QM>(tk, wc2, L2);
+        asm volatile("" ::: "memory");
+    };
+    // table pairs of groups without a record at some step are read at index
+    // 0: make every pair's entries 0 and 16 zero once
+    if (bl) {
+        tw[(kb * S + rb) * kZPair] = 0.0;
+        tw[(kb * S + rb) * kZPair + 16] = 0.0;
+    }
+    double hA[S], hB[S];
+    uint64_t wA1, wA2, wB1, wB2;
+    if (0 < nsteps) issue(0, hA, wA1, wA2);
+    if (1 < nsteps) issue(1, hB, wB1, wB2);
+    for (uint32_t st = 0; st < nsteps; st += 2) {
+        process(st, hA, wA1, wA2);
+        if (st + 2 < nsteps) issue(st + 2, hA, wA1, wA2);
+        if (st + 1 >= nsteps) break;
+        process(st + 1, hB, wB1, wB2);
+        if (st + 3 < nsteps) issue(st + 3, hB, wB1, wB2);
+    }
+    // draw: group g draws node 4 Q + g with word g of its chains' quad calls
+    const Words wq1 = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                    (kPhasePrimal << 30) | (uint32_t)c1, t, g.rk);
+    const Words wq2 = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
+                                    (kPhasePrimal << 30) | (uint32_t)c2, t, g.rk);
+    const bool drawn = nin && !hub_g;
+    const int nx1 = draw_node<QM, UQ, EXP64>(L1, qn, word_at(wq1, grp) >> 8);
+    const int nx2 = draw_node<QM, UQ, EXP64>(L2, qn, word_at(wq2, grp) >> 8);
+    if (drawn && cv1) g.x[node * g.C + c1] = (uint8_t)nx1;
+    if (drawn && cv2) g.x[node * g.C + c2] = (uint8_t)nx2;
+    if (count) {
+        // the wave owns the quad's counters (one chain block): row j QM + a
+        uint32_t *cq = g.counts + quad * 4 * QM;
+        uint32_t row = 0;
+        uint64_t wmask = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int a = 0; a < QM; ++a) {
+                const bool mine = drawn && grp == j;
+                const uint32_t add = (uint32_t)__popcll(__ballot(mine && cv1 && nx1 == a)) +
+                                     (uint32_t)__popcll(__ballot(mine && cv2 && nx2 == a));
+                row = pdg_writelane_i32(cq[j * QM + a] + add, j * QM + a, row);
+            }
+            const uint64_t dj = __ballot(drawn && grp == j && lane == 16 * j);
+            const int qj = UQ ? QM : __shfl(qn, 16 * j);
+            if (dj) wmask |= ((1ull << qj) - 1ull) << (j * QM);
+        }
+        if (lane_bit(wmask)) cq[lane] = row;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // a4 for hubs.  A node with more than kHubThreshold incidence entries is a
 // hub: the quad kernels skip it, and its records are split into pieces of at
 // most kHubPiece so that one hub's work spreads over many waves.
@@ -1251,6 +1533,103 @@ __global__ __launch_bounds__(256) void k_hub_pieces(Graph g, int64_t np,
 #pragma unroll
     for (int s = 1; s < QM; ++s)
         part[((piece * CB + cb) * (QM - 1) + (s - 1)) * 64 + lane] = L[s];
+}
+
+// k_hub_pieces for chain-major dual words (17..32 chains, q_max >= 6): one
+// wave per piece, lanes, tables and the two chunk buffers as in k_primal32z;
+// the piece's partial field of chain l % 32 goes to lane l of its rows of
+// part (as k_hub_finish with 32 chains per item reads it).
+template <int QM>
+__global__ __launch_bounds__(256) void k_hub_pieces_z(Graph g, int64_t np,
+                                                      const uint32_t *__restrict__ pnode,
+                                                      const uint32_t *__restrict__ pfirst,
+                                                      const uint32_t *__restrict__ pn,
+                                                      double *__restrict__ part)
+{
+    constexpr int D = dim_d(QM);
+    constexpr int S = QM - 1;
+    constexpr int G = 4;
+    constexpr int K = kZChunk;
+    constexpr int KG = K / G;
+    __shared__ __align__(16) double tab[4][K * S * kZPair];
+    const int lane = threadIdx.x & 63;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t piece = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    if (piece >= np) return;
+    const int grp = lane >> 4;
+    const int c1 = lane & 15, c2 = c1 + 16;
+    const bool cv1 = c1 < g.C, cv2 = c2 < g.C;
+    const uint32_t node = pnode[piece];
+    const uint64_t rbase = (uint64_t)g.inc_off[node] + pfirst[piece];
+    const uint32_t n = pn[piece];
+    double *tw = tab[wib];
+    const int kb = lane / S, rb = lane % S;
+    const bool bl = lane < K * S;
+    const uint64_t *z64 = reinterpret_cast<const uint64_t *>(g.rec_z);
+    const uint64_t C = (uint64_t)g.C;
+    auto issue = [&](uint32_t first, double (&h)[S], uint64_t (&w1)[KG], uint64_t (&w2)[KG]) {
+        const uint32_t nrec = min(n - first, (uint32_t)K);
+        const uint64_t r0 = rbase + first;
+        const bool hb = bl && (uint32_t)kb < nrec;
+        const double *hp = g.rec_p + (r0 + (uint64_t)kb) * D + rb * S;
+#pragma unroll
+        for (int o = 0; o < S; ++o) h[o] = hb ? hp[o] : 0.0;
+#pragma unroll
+        for (int i = 0; i < KG; ++i) {
+            const uint32_t k = (uint32_t)(grp + G * i);
+            const bool has = k < nrec;
+            w1[i] = has && cv1 ? z64[(r0 + k) * C + c1] : 0ull;
+            w2[i] = has && cv2 ? z64[(r0 + k) * C + c2] : 0ull;
+        }
+    };
+    double L1[QM], L2[QM];
+#pragma unroll
+    for (int a = 0; a < QM; ++a) L1[a] = L2[a] = 0.0;
+    auto process = [&](uint32_t first, const double (&hc)[S], const uint64_t (&wc1)[KG],
+                       const uint64_t (&wc2)[KG]) {
+        const uint32_t nrec = min(n - first, (uint32_t)K);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (bl && (uint32_t)kb < nrec) build_tables<QM>(hc, tw + (kb * S + rb) * kZPair);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < KG; ++i) {
+            const uint32_t k = (uint32_t)(grp + G * i);
+            const double *tk = tw + (k < nrec ? k : 0u) * (S * kZPair);
+            add_tables<QM>(tk, wc1[i], L1);
+            asm volatile("" ::: "memory");
+            add_tables<QM>(tk, wc2[i], L2);
+            asm volatile("" ::: "memory");
+        }
+    };
+    double hA[S], hB[S];
+    uint64_t wA1[KG], wA2[KG], wB1[KG], wB2[KG];
+    uint32_t fA = 0, fB = K;  // first record of the chunk in each buffer
+    if (fA < n) issue(fA, hA, wA1, wA2);
+    if (fB < n) issue(fB, hB, wB1, wB2);
+    while (fA < n) {
+        process(fA, hA, wA1, wA2);
+        fA += 2 * K;
+        if (fA < n) issue(fA, hA, wA1, wA2);
+        if (fB >= n) break;
+        process(fB, hB, wB1, wB2);
+        fB += 2 * K;
+        if (fB < n) issue(fB, hB, wB1, wB2);
+    }
+#pragma unroll
+    for (int s = 1; s < QM; ++s) {
+        L1[s] += __shfl_xor(L1[s], 16);
+        L2[s] += __shfl_xor(L2[s], 16);
+    }
+#pragma unroll
+    for (int s = 1; s < QM; ++s) {
+        L1[s] += __shfl_xor(L1[s], 32);
+        L2[s] += __shfl_xor(L2[s], 32);
+    }
+#pragma unroll
+    for (int s = 1; s < QM; ++s)
+        part[(piece * (QM - 1) + (s - 1)) * 64 + lane] = (lane & 16) ? L2[s] : L1[s];
 }
 
 template <int QM, bool UQ, bool EXP64, int LPI>
@@ -1824,12 +2203,11 @@ __global__ void k_get_duals(int64_t m, int32_t QM, Graph g, const int32_t *__res
     const int64_t s = slots[k];
     const uint32_t sq = g.sq[s];
     const int qs = (int)(sq & 15u), qd = (int)(sq >> 4);
-    const int D = (QM - 1) * (QM - 1);
     const uint64_t r0 = g.ipos[2 * s];
     uint64_t bits = 0;
     for (int d = 0; d < (qs - 1) * (qd - 1); ++d) {
         const int dp = (d / (qd - 1)) * (QM - 1) + d % (qd - 1);
-        bits |= (uint64_t)((g.rec_z[rec_zword(g, r0, dp, c, D)] >> (c & 31)) & 1u) << d;
+        bits |= (uint64_t)rec_theta(g, r0, dp, c, QM) << d;
     }
     out[idx] = bits;
 }
@@ -1952,6 +2330,7 @@ __global__ __launch_bounds__(256) void k_logv_nodes(Graph g, double *__restrict_
     const int wib = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int cb = blockIdx.y, c = cb * 64 + lane;
     const bool cv = c < g.C;
+    const bool zc = zc_layout(QM, g.C);
     const int64_t quad = (int64_t)blockIdx.x * 4 + wib;
     // the quad's headers first
     uint32_t off[4], cnt[4];
@@ -1982,11 +2361,23 @@ __global__ __launch_bounds__(256) void k_logv_nodes(Graph g, double *__restrict_
             for (int u = 0; u < U; ++u) {
                 const uint32_t rr = r + u < end ? r + u : end - 1;
                 const double *h = g.rec_p + (uint64_t)rr * D;
-                const uint32_t *z = g.rec_z + rec_zword(g, rr, 0, c, D);
+                if (zc) {
+                    // chain-major words: chain c's bit of entry dp moved to bit c
+                    const uint64_t wz =
+                        cv ? reinterpret_cast<const uint64_t *>(g.rec_z)[(uint64_t)rr * g.C + c] : 0ull;
 #pragma unroll
-                for (int dp = 0; dp < D; ++dp) {
-                    hv[u][dp] = h[dp];
-                    zw[u][dp] = z[dp * ZS];
+                    for (int dp = 0; dp < D; ++dp) {
+                        hv[u][dp] = h[dp];
+                        zw[u][dp] = ((uint32_t)(wz >> (8 * (dp / (QM - 1)) + dp % (QM - 1))) & 1u)
+                                    << (c & 31);
+                    }
+                } else {
+                    const uint32_t *z = g.rec_z + rec_zword(g, rr, 0, c, D);
+#pragma unroll
+                    for (int dp = 0; dp < D; ++dp) {
+                        hv[u][dp] = h[dp];
+                        zw[u][dp] = z[dp * ZS];
+                    }
                 }
             }
 #pragma unroll

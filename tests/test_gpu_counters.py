@@ -7,7 +7,7 @@ state and every counter must equal the oracle's.  The sweeps are launched one
 phase at a time, so small graphs do not take the one-launch path and each case
 reaches the kernel it names: the chain count picks the shape (1..16 chains:
 k_primal, or k_primal_st for q_max >= 3 with 8 or 16 chains; 17..32:
-k_primal32; 33 or more: k_primal64, ragged chain blocks above 64), and nodes
+k_primal32, or k_primal32z for q_max >= 6; 33 or more: k_primal64, ragged chain blocks above 64), and nodes
 with more than 256 incidences go through k_hub_pieces + k_hub_finish (its
 counters owned by one wave for one chain block, added atomically for more).
 """
@@ -34,8 +34,10 @@ def _cases():
     f64 = np.float64
     yield "primal64_q4_C100", W.table_grid(20, 20, 4, seed=1, dtype="f64"), 100
     yield "primal64_mixed_C64", W.random_graph(300, 700, [2, 3, 6], seed=2), 64
-    yield "primal32_q8_C20", W.random_graph(200, 500, [8], seed=3), 20
-    yield "primal32_q8_C32", W.random_graph(200, 500, [8], seed=4), 32
+    yield "primal32_q5_C20", W.random_graph(200, 500, [5], seed=3), 20
+    yield "primal32z_q8_C20", W.random_graph(200, 500, [8], seed=3), 20
+    yield "primal32z_q8_C32", W.random_graph(200, 500, [8], seed=4), 32
+    yield "primal32z_mixed_q67_C24", W.random_graph(200, 500, [6, 7], seed=12), 24
     yield "primal_st_q35_C8", W.random_graph(300, 800, [3, 5], seed=5), 8
     yield "primal_st_q5_C16", W.random_graph(300, 800, [5], seed=6), 16
     yield "primal_st_q3_C8", W.random_graph(300, 800, [3], seed=7), 8
@@ -44,6 +46,7 @@ def _cases():
     yield "primal_q2_C16", W.ising_grid(20, 20, seed=10, J_half_range=0.6), 16
     yield "primal_mixed_C5", W.random_graph(300, 700, [2, 4, 7], seed=11), 5
     yield "hubs_mixed_C32", _hub_graph(700, [2, 3, 5], 4, 9, f64), 32
+    yield "hubs_z_q8_C32", _hub_graph(500, [8], 2, 13, f64), 32
     yield "hubs_q2_C100", _hub_graph(600, [2], 2, 10, f64), 100
     yield "hubs_q4_C16", _hub_graph(900, [4], 3, 8, f64), 16
     yield "hubs_q2_C1", _hub_graph(600, [2], 2, 10, f64), 1

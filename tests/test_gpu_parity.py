@@ -119,6 +119,13 @@ def _models():
     # q_max 8 with 8 chains: a step's records do not fit the piece kernel's
     # LDS chunk, so hubs stay with the quad kernel
     yield "hubs_q8_f32_C8", _hub_graph(500, [8], 2, 13), 8
+    # 17..32 chains with q_max >= 6: chain-major dual words, table-based primal
+    # and hub pieces; uniform and mixed q (entries of smaller tables, binary
+    # nodes), ragged chain counts
+    yield "random_q6_f32_C24", W.random_graph(300, 900, [6], seed=26, dtype="f32"), 24
+    yield "random_mixed_q267_f32_C29", W.random_graph(300, 800, [2, 6, 7], seed=27, dtype="f32"), 29
+    yield "hubs_q8_f32_C32", _hub_graph(500, [8], 2, 13), 32
+    yield "hubs_mixed_q68_f64_C20", _hub_graph(600, [6, 8], 3, 16, np.float64), 20
 
 
 def _hub_graph(n, qs, n_hubs, seed, dtype=np.float32):
