@@ -1297,8 +1297,8 @@ __device__ __forceinline__ void add_tables(const double *__restrict__ tk, uint64
 // pairs are built into the wave's LDS region by the first 4 (QM-1) lanes
 // (lane (QM-1) g + r - 1 builds the pair of own state r of group g's record
 // from the h row it loaded) and read back by the group's lanes.  Loads run
-// through two register buffers, so while one step is processed the next two
-// are in flight.  No cross-group sum is needed and the four nodes are drawn
+// through three register buffers, so while one step is processed the next
+// two are in flight.  No cross-group sum is needed and the four nodes are drawn
 // at once; a wave takes as many steps as its busiest node has records.
 // ---------------------------------------------------------------------------
 template <int QM, bool UQ, bool EXP64>
@@ -1348,15 +1348,19 @@ __global__ __launch_bounds__(256) void k_primal32z(Graph g, uint32_t t, int coun
     double *tw = tab[wib];
     const uint64_t *z64 = reinterpret_cast<const uint64_t *>(g.rec_z);
     const uint64_t C = (uint64_t)g.C;
+    // loads are unconditional and raw (lanes without a record read the
+    // pool's first one); the predicates are applied where the values are used,
+    // so nothing waits on a load before its step and the later steps' loads
+    // stay in flight
+    const int cz2 = cv2 ? c2 : c1;
     auto issue = [&](uint32_t st, double (&h)[S], uint64_t &w1, uint64_t &w2) {
         const bool hb = bl && st < cnt_b;
-        const double *hp = g.rec_p + ((uint64_t)off_b + st) * D + rb * S;
+        const double *hp = g.rec_p + (hb ? ((uint64_t)off_b + st) * D + rb * S : 0ull);
 #pragma unroll
-        for (int o = 0; o < S; ++o) h[o] = hb ? hp[o] : 0.0;
-        const bool has = st < cnt_g;
-        const uint64_t r = (uint64_t)off_g + st;
-        w1 = has && cv1 ? z64[r * C + c1] : 0ull;
-        w2 = has && cv2 ? z64[r * C + c2] : 0ull;
+        for (int o = 0; o < S; ++o) h[o] = hp[o];
+        const uint64_t r = st < cnt_g ? (uint64_t)off_g + st : 0ull;
+        w1 = z64[r * C + c1];
+        w2 = z64[r * C + cz2];
     };
     const int qn = UQ ? QM : (nin ? (int)g.q[node] : QM);
     double L1[QM], L2[QM];
@@ -1372,12 +1376,13 @@ __global__ __launch_bounds__(256) void k_primal32z(Graph g, uint32_t t, int coun
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         // a group whose node has no record at this step reads its table pair
-        // at index 0 (0.0): its word is 0; those tables were built at step 0
-        // or hold zeros written below
+        // at index 0 (0.0) with a zero word; those tables were built at an
+        // earlier step or hold the zeros written below
+        const bool has = st < cnt_g;
         const double *tk = tw + grp * (S * kZPair);
-        add_tables<QM>(tk, wc1, L1);
+        add_tables<QM>(tk, has ? wc1 : 0ull, L1);
         asm volatile("" ::: "memory");
-        add_tables<QM>(tk, wc2, L2);
+        add_tables<QM>(tk, has && cv2 ? wc2 : 0ull, L2);
         asm volatile("" ::: "memory");
     };
     // table pairs of groups without a record at some step are read at index
@@ -1386,16 +1391,20 @@ __global__ __launch_bounds__(256) void k_primal32z(Graph g, uint32_t t, int coun
         tw[(kb * S + rb) * kZPair] = 0.0;
         tw[(kb * S + rb) * kZPair + 16] = 0.0;
     }
-    double hA[S], hB[S];
-    uint64_t wA1, wA2, wB1, wB2;
+    double hA[S], hB[S], hC[S];
+    uint64_t wA1, wA2, wB1, wB2, wC1, wC2;
     if (0 < nsteps) issue(0, hA, wA1, wA2);
     if (1 < nsteps) issue(1, hB, wB1, wB2);
-    for (uint32_t st = 0; st < nsteps; st += 2) {
+    if (2 < nsteps) issue(2, hC, wC1, wC2);
+    for (uint32_t st = 0; st < nsteps; st += 3) {
         process(st, hA, wA1, wA2);
-        if (st + 2 < nsteps) issue(st + 2, hA, wA1, wA2);
+        if (st + 3 < nsteps) issue(st + 3, hA, wA1, wA2);
         if (st + 1 >= nsteps) break;
         process(st + 1, hB, wB1, wB2);
-        if (st + 3 < nsteps) issue(st + 3, hB, wB1, wB2);
+        if (st + 4 < nsteps) issue(st + 4, hB, wB1, wB2);
+        if (st + 2 >= nsteps) break;
+        process(st + 2, hC, wC1, wC2);
+        if (st + 5 < nsteps) issue(st + 5, hC, wC1, wC2);
     }
     // draw: group g draws node 4 Q + g with word g of its chains' quad calls
     const Words wq1 = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
@@ -1567,19 +1576,21 @@ __global__ __launch_bounds__(256) void k_hub_pieces_z(Graph g, int64_t np,
     const bool bl = lane < K * S;
     const uint64_t *z64 = reinterpret_cast<const uint64_t *>(g.rec_z);
     const uint64_t C = (uint64_t)g.C;
+    // unconditional raw loads, predicates applied at use (as in k_primal32z)
+    const int cz2 = cv2 ? c2 : c1;
     auto issue = [&](uint32_t first, double (&h)[S], uint64_t (&w1)[KG], uint64_t (&w2)[KG]) {
         const uint32_t nrec = min(n - first, (uint32_t)K);
         const uint64_t r0 = rbase + first;
         const bool hb = bl && (uint32_t)kb < nrec;
-        const double *hp = g.rec_p + (r0 + (uint64_t)kb) * D + rb * S;
+        const double *hp = g.rec_p + (hb ? (r0 + (uint64_t)kb) * D + rb * S : 0ull);
 #pragma unroll
-        for (int o = 0; o < S; ++o) h[o] = hb ? hp[o] : 0.0;
+        for (int o = 0; o < S; ++o) h[o] = hp[o];
 #pragma unroll
         for (int i = 0; i < KG; ++i) {
             const uint32_t k = (uint32_t)(grp + G * i);
-            const bool has = k < nrec;
-            w1[i] = has && cv1 ? z64[(r0 + k) * C + c1] : 0ull;
-            w2[i] = has && cv2 ? z64[(r0 + k) * C + c2] : 0ull;
+            const uint64_t r = k < nrec ? r0 + k : 0ull;
+            w1[i] = z64[r * C + c1];
+            w2[i] = z64[r * C + cz2];
         }
     };
     double L1[QM], L2[QM];
@@ -1596,10 +1607,11 @@ __global__ __launch_bounds__(256) void k_hub_pieces_z(Graph g, int64_t np,
 #pragma unroll
         for (int i = 0; i < KG; ++i) {
             const uint32_t k = (uint32_t)(grp + G * i);
-            const double *tk = tw + (k < nrec ? k : 0u) * (S * kZPair);
-            add_tables<QM>(tk, wc1[i], L1);
+            const bool has = k < nrec;
+            const double *tk = tw + (has ? k : 0u) * (S * kZPair);
+            add_tables<QM>(tk, has ? wc1[i] : 0ull, L1);
             asm volatile("" ::: "memory");
-            add_tables<QM>(tk, wc2[i], L2);
+            add_tables<QM>(tk, has && cv2 ? wc2[i] : 0ull, L2);
             asm volatile("" ::: "memory");
         }
     };
