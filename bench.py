@@ -109,25 +109,39 @@ def host_info():
     return info
 
 
+def chain_major(model, C):
+    """Whether the context keeps its dual words chain-major (one 64-bit word per
+    chain and record): 17..32 chains with q_max >= 6."""
+    return model.q_max >= 6 and 17 <= C <= 32
+
+
+def record_words(model, C, D):
+    """Bytes of dual words per incidence record with D entries: chain-major 8 C;
+    otherwise one chain mask per entry, 4 D bytes (C <= 32) or 8 D per block of
+    64 chains."""
+    if chain_major(model, C):
+        return 8 * C
+    return 4 * D if C <= 32 else 8 * D * ((C + 63) // 64)
+
+
 def primal_bytes(model, C):
-    """Algorithmic HBM bytes of one primal phase with C <= 32 chains: per
-    incidence the record's h (8 D bytes, FP64) and its D dual words (4 D bytes,
-    one 32-bit chain mask per entry), D = (q_node - 1)(q_other - 1); per node its
-    base row (8 q_max), new states (C), counters read and written (8 q_max) and
-    segment offset and count (8)."""
+    """Algorithmic HBM bytes of one primal phase: per incidence the record's h
+    (8 D bytes, FP64) and its dual words (record_words), D = (q_node - 1)
+    (q_other - 1); per node its base row (8 q_max), new states (C), counters
+    read and written (8 q_max) and segment offset and count (8)."""
     D = (model.q[model.src].astype(np.int64) - 1) * (model.q[model.dst] - 1)
     qm = model.q_max
-    return int(2 * (12 * D).sum() + model.n * (16 * qm + C + 8))
+    return int(2 * (8 * D + record_words(model, C, D)).sum() + model.n * (16 * qm + C + 8))
 
 
 def dual_bytes(model, C):
-    """Algorithmic HBM bytes of one dual phase over `model` with C <= 32 chains
-    (records of 32-bit mask words): per edge with D = (q_src-1)(q_dst-1) entries,
-    slot metadata (uid 8, src 4, dst 4, record positions 8), the sign word (8) and
-    D threshold pairs (8 D), the endpoint states (2 C bytes) and the D mask words
-    written to each of the two records (8 D)."""
+    """Algorithmic HBM bytes of one dual phase: per edge with D =
+    (q_src-1)(q_dst-1) entries, slot metadata (uid 8, src 4, dst 4, record
+    positions 8), the sign word (8) and D threshold pairs (8 D), the endpoint
+    states (2 C bytes) and the dual words written to each of the two records
+    (record_words)."""
     D = (model.q[model.src].astype(np.int64) - 1) * (model.q[model.dst] - 1)
-    return int((32 + 2 * C + 16 * D).sum())
+    return int((32 + 2 * C + 8 * D + 2 * record_words(model, C, D)).sum())
 
 
 def parse():
@@ -249,6 +263,8 @@ def run_plain(args):
     updates = C * (model.n + model.m)
     draws_per_launch = model.m * 9 * C
     achieved = draws_per_launch * DRAW_SLOTS / (dual_ms / 1e3)
+    pbytes = primal_bytes(model, C)
+    p_gbs = pbytes / (primal_ms / 1e3) / 1e9
     out = {
         "metric": "chain*(|V|+|E|) updates/s",
         "value": updates * steps / (total_ms / 1e3),
@@ -267,6 +283,11 @@ def run_plain(args):
                                                 "k_dual64<4,true,4>"),
                      "kernel": "k_dual64<4,true,4>",
                      "work_per_draw_slots": DRAW_SLOTS},
+        "roofline_primal": {"bound": "hbm", "achieved": p_gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": p_gbs / HBM_PEAK_GBS,
+                            "traffic": profile_traffic("plain_grid_sweep_kernels.txt",
+                                                       "primal_phase"),
+                            "kernel": "k_primal64<4,true,false>", "algorithmic_bytes": pbytes},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(model, C, seed, "2 sweeps of the full workload", sweeps=2)
@@ -401,7 +422,7 @@ def run_dynamic(args):
                             "unit": "GB/s", "frac": p_gbs / HBM_PEAK_GBS,
                             "traffic": profile_traffic("dynamic_sparse_sweep_kernels.txt",
                                                        "primal_phase"),
-                            "kernel": "primal phase (k_primal32 + hub pieces + hub finish)",
+                            "kernel": "primal phase (k_primal32z + hub pieces + hub finish)",
                             "algorithmic_bytes": pbytes},
     }
     del model

@@ -96,6 +96,31 @@ def test_dual_bytes_counts_each_edge_by_its_states():
     assert bench.dual_bytes(m, C) == sum(32 + 2 * C + 16 * d for d in Ds)
 
 
+def test_byte_models_of_chain_major_words():
+    """With 17..32 chains and q_max >= 6 each record carries one 64-bit word per
+    chain: 8 C bytes per record written by the dual (two records per edge) and
+    read by the primal, in place of 4 D bytes of 32-bit mask words (8 D per
+    block of 64 chains above 32 chains)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    q = np.array([6, 6, 2], np.int32)
+    src = np.array([0, 1], np.int32)
+    dst = np.array([1, 2], np.int32)
+    m = W.Model(q, np.zeros((3, 6), np.float32), src, dst, np.zeros((2, 6, 6), np.float32))
+    Ds = [5 * 5, 5 * 1]
+    for C, chain_major in [(16, False), (17, True), (32, True), (33, False), (130, False)]:
+        if chain_major:
+            words = [8 * C] * 2
+        elif C <= 32:
+            words = [4 * d for d in Ds]
+        else:  # one 64-bit mask per entry and block of 64 chains
+            words = [8 * d * ((C + 63) // 64) for d in Ds]
+        assert bench.chain_major(m, C) == chain_major
+        assert bench.dual_bytes(m, C) == sum(32 + 2 * C + 8 * d + 2 * w for d, w in zip(Ds, words))
+        assert bench.primal_bytes(m, C) == (2 * sum(8 * d + w for d, w in zip(Ds, words))
+                                            + 3 * (16 * 6 + C + 8))
+
+
 def test_batch_by_states_equals_grouped_batch():
     """The per-state-count batch generator draws the same graphs, tables and
     unaries as the padded one-model batch split by state count."""
