@@ -295,6 +295,20 @@ struct LaneMap {
 extern "C" __device__ uint32_t pdg_writelane_i32(uint32_t value, uint32_t lane, uint32_t old)
     __asm("llvm.amdgcn.writelane.i32");
 
+// 8 x 8 bit-matrix transpose of a 64-bit word (bit 8 r + c -> bit 8 c + r) by
+// three delta swaps: a record word in the src orientation (byte = own state)
+// becomes the same duals in the dst orientation.
+__device__ __forceinline__ uint64_t transpose8x8(uint64_t x)
+{
+    uint64_t t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+    x ^= t ^ (t << 7);
+    t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+    x ^= t ^ (t << 14);
+    t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+    x ^= t ^ (t << 28);
+    return x;
+}
+
 // Wave-uniform lane mask -> per-lane predicate without VALU work.
 __device__ __forceinline__ bool lane_bit(uint64_t mask)
 {
@@ -399,7 +413,7 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
     uint32_t outr[NREG];
 #pragma unroll
     for (int r = 0; r < NREG; ++r) outr[r] = 0u;
-    uint32_t zs[2] = {0u, 0u}, zd[2] = {0u, 0u};  // ZC: src and dst record words of this chain
+    uint32_t zs[2] = {0u, 0u};  // ZC: this chain's src record word
     const bool leader = !ZC && live && (lm.lane % LPI == 0);
     // records of the two endpoints receive the masks
     const uint64_t r0 = live ? g.ipos[2 * sl] : 0ull, r1 = live ? g.ipos[2 * sl + 1] : 0ull;
@@ -438,22 +452,19 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
             uint64_t zm = cp | (ch & (yh | yb)) | (cm & yh & yb);
             if (!UQ) zm &= __ballot(dd < De) & mact;
             if constexpr (ZC) {
-                // bit 8 (a-1) + (b-1) of the src word, 8 (b-1) + (a-1) of the dst word
+                // bit 8 (a-1) + (b-1) of the src word (the dst word is its
+                // transpose, formed at the end)
                 const int ai = UQ ? dd / (QM - 1) : a - 1, bi = UQ ? dd % (QM - 1) : b - 1;
                 const uint32_t th = lane_bit(zm) ? 1u : 0u;
-                const int ps = 8 * ai + bi, pd = 8 * bi + ai;
+                const int ps = 8 * ai + bi;
                 if (UQ) {
                     zs[ps >> 5] |= th << (ps & 31);
-                    zd[pd >> 5] |= th << (pd & 31);
                 } else {
                     // entries past the edge's own carry th = 0
-                    const uint32_t vs = th << (ps & 31), vd = th << (pd & 31);
+                    const uint32_t vs = th << (ps & 31);
                     zs[0] |= ps < 32 ? vs : 0u;
                     zs[1] |= ps < 32 ? 0u : vs;
-                    zd[0] |= pd < 32 ? vd : 0u;
-                    zd[1] |= pd < 32 ? 0u : vd;
                 }
-
             } else if (GATHER) {
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
@@ -482,8 +493,6 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
             // (an identity DPP move: opaque to the compiler, costs one VALU)
             zs[0] = __builtin_amdgcn_mov_dpp((int)zs[0], 0xE4, 0xF, 0xF, false);
             zs[1] = __builtin_amdgcn_mov_dpp((int)zs[1], 0xE4, 0xF, 0xF, false);
-            zd[0] = __builtin_amdgcn_mov_dpp((int)zd[0], 0xE4, 0xF, 0xF, false);
-            zd[1] = __builtin_amdgcn_mov_dpp((int)zd[1], 0xE4, 0xF, 0xF, false);
         }
     }
     // GATHER: the gathered mask words go out to both records, each in its
@@ -492,9 +501,10 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
     // holds item p's word of entry d, so consecutive lanes fill one record.
     if constexpr (ZC) {
         if (active) {
-            uint2 *z = reinterpret_cast<uint2 *>(g.rec_z);
-            z[r0 * (uint64_t)g.C + lm.c] = make_uint2(zs[0], zs[1]);
-            z[r1 * (uint64_t)g.C + lm.c] = make_uint2(zd[0], zd[1]);
+            const uint64_t ws = ((uint64_t)zs[1] << 32) | zs[0];
+            uint64_t *z = reinterpret_cast<uint64_t *>(g.rec_z);
+            z[r0 * (uint64_t)g.C + lm.c] = ws;
+            z[r1 * (uint64_t)g.C + lm.c] = transpose8x8(ws);
         }
         return;
     }
