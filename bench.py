@@ -31,8 +31,8 @@ primal phase over every node and chain (with marginal counting).  The metric is
 chain * (|V| + |E|) updates/s with every input resident in HBM.
 
 Prints one JSON line.  ``roofline`` describes the dominant kernel, the dual:
-it is bound by integer VALU work (Philox draws), so achieved and peak are VALU
-issue slots per second.  ``roofline_primal`` puts the primal phase against the
+it is bound by integer ALU work (Philox draws and their decision logic), so
+achieved and peak are full-rate 32-bit lane-operation slots per second.  ``roofline_primal`` puts the primal phase against the
 HBM roof (algorithmic bytes: the h records and dual words of every incidence,
 per node its base row, state and counters).  ``traffic`` (HBM bytes per launch
 from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a plain copy) is read from the
@@ -56,13 +56,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # ---- VALU roofline of the dual kernel ---------------------------------------
-# Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 full-rate 32-bit VALU
-# lane-operations per second.  Algorithmic work of one dual draw, in full-rate
-# issue slots: one fifth of a Philox4x32-10 call -- 10 rounds, each two 32x32->64
-# multiplies (v_mad_u64_u32, measured full rate on gfx950) and two three-input
-# xors (v_bitop3_b32) -- plus three compares that decide the draw (11 slots).
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-PHILOX_SLOTS = 10 * (2 + 2)
+# Peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6e12 full-rate 32-bit VALU
+# lane-operations per second (the chip's 157.3 TFLOP/s FP32 vector rate counts
+# an FMA as two).  Algorithmic work of one dual draw, in those slots: one fifth
+# of a Philox4x32-10 call plus the three compares that decide the draw.  A call
+# is 10 rounds of two 32x32->64 multiplies (v_mad_u64_u32, not a full-rate op)
+# and two three-input xors; its cost is the measured one, 78.3 slots (the chip
+# runs 1.00e12 calls/s with every lane busy: profiles/valu_rates.txt), so a
+# draw is 78.3 / 5 + 3 = 18.7 slots.
+PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
+PHILOX_SLOTS = 78.3
 DRAW_SLOTS = PHILOX_SLOTS / 5.0 + 3.0
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
@@ -296,9 +299,9 @@ def run_plain(args):
 
 def dynamic_cpu_baseline(q, C, seed, every):
     """The oracle on a bounded sample of the dynamic workload: the same recipe at
-    2^19 nodes (an eighth of the nodes and edges), one sweep of all C chains
-    followed by one churn step (1 % of the edges removed, as many inserted and
-    decomposed), then the same sweep with one chain on one core."""
+    2^19 nodes (an eighth of the nodes and edges), one sweep of all C chains, one
+    churn step (1 % of the edges removed, as many inserted and decomposed), a
+    second sweep on the edited graph; then one sweep with one chain on one core."""
     from oracle import oracle
     from paper_1611_06684_amd import workloads as W
     n = 1 << 19
@@ -311,6 +314,7 @@ def dynamic_cpu_baseline(q, C, seed, every):
     t0 = time.perf_counter()
     oracle.run(model, dec, uid, seed, x, 0, 1, burn_in=0)
     t_sweep = time.perf_counter() - t0
+    t1 = time.perf_counter()
     rem, ns, nd, nL = churn.next_batch(uid)
     keep = ~np.isin(uid, rem)
     cur = W.Model(model.q, model.lam, np.concatenate([model.src[keep], ns]),
@@ -320,23 +324,26 @@ def dynamic_cpu_baseline(q, C, seed, every):
                                 np.concatenate([dec.rrow[keep], new.rrow]),
                                 np.concatenate([dec.rcol[keep], new.rcol]))
     uid2 = np.concatenate([uid[keep], uid[-1] + 1 + np.arange(len(ns), dtype=np.uint64)])
-    t_edit = time.perf_counter() - t0 - t_sweep
+    t_edit = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    oracle.run(cur, dec2, uid2, seed, x, 1, 1, burn_in=0)
+    t_sweep2 = time.perf_counter() - t2
     dt = time.perf_counter() - t0
-    ups = C * (model.n + model.m) / (t_sweep + t_edit / every)
+    ups = C * ((model.n + model.m) + (cur.n + cur.m)) / (t_sweep + t_sweep2 + 2 * t_edit / every)
     threads = min(oracle.num_threads(), C)
     oracle.set_threads(1)
     x1 = np.ascontiguousarray(x[:, :1])
-    t1 = time.perf_counter()
-    oracle.run(cur, dec2, uid2, seed, x1, 1, 1, burn_in=0)
-    t_one = time.perf_counter() - t1
+    t3 = time.perf_counter()
+    oracle.run(cur, dec2, uid2, seed, x1, 2, 1, burn_in=0)
+    t_one = time.perf_counter() - t3
     oracle.set_threads(threads)
     oracle.use_library(None)
     return {"value": ups, "unit": "updates/s", "cores": threads, "kind": "oracle",
-            "sample": (f"the dynamic recipe at 2^19 nodes ({model.m} edges): 1 sweep of {C} "
-                       f"chains ({t_sweep:.2f} s) + 1 churn step of {len(ns)} removals and "
-                       f"insertions ({t_edit:.2f} s, charged as 1/{every} per sweep), "
-                       f"{dt:.1f} s wall"),
-            "single_core": {"value": (model.n + cur.m) / t_one, "unit": "updates/s",
+            "sample": (f"the dynamic recipe at 2^19 nodes ({model.m} edges): 2 sweeps of {C} "
+                       f"chains ({t_sweep:.2f} s, {t_sweep2:.2f} s) around 1 churn step of "
+                       f"{len(ns)} removals and insertions ({t_edit:.2f} s, charged as 1/{every} "
+                       f"per sweep), {dt:.1f} s wall"),
+            "single_core": {"value": (cur.n + cur.m) / t_one, "unit": "updates/s",
                             "sample": f"1 sweep of 1 chain on 1 thread, {t_one:.2f} s"},
             "compile": flags, "host": host_info()}
 

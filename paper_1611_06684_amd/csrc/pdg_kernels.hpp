@@ -1576,8 +1576,8 @@ __global__ __launch_bounds__(256) void k_hub_pieces_z(Graph g, int64_t np,
     const int64_t piece = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
     if (piece >= np) return;
     const int grp = lane >> 4;
-    const int c1 = lane & 15, c2 = c1 + 16;
-    const bool cv1 = c1 < g.C, cv2 = c2 < g.C;
+    const int c1 = lane & 15, c2 = c1 + 16;  // c1 < 17 <= C: always a chain
+    const bool cv2 = c2 < g.C;
     const uint32_t node = pnode[piece];
     const uint64_t rbase = (uint64_t)g.inc_off[node] + pfirst[piece];
     const uint32_t n = pn[piece];

@@ -23,13 +23,14 @@ def test_header_and_binding_agree():
     declared = _declared()
     assert len(declared) >= 20
     assert sorted(pdg.EXPORTS) == declared
-    from paper_1611_06684_amd import pdg_block
+    from paper_1611_06684_amd import pdg_block, rates
     assert sorted(pdg_block.EXPORTS) == _declared("pdg_block.h")
+    assert sorted(rates.EXPORTS) == _declared("pdg_rates.h")
 
 
 def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(pdg.LIB_PATH)
-    for name in _declared() + _declared("pdg_block.h"):
+    for name in _declared() + _declared("pdg_block.h") + _declared("pdg_rates.h"):
         assert hasattr(L, name), name
 
 
