@@ -390,6 +390,22 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
     const uint8_t *blk = g.dparams + sl * thr_bytes(QM);
     const uint64_t sign = *reinterpret_cast<const uint64_t *>(blk);
     const uint32_t *thr = reinterpret_cast<const uint32_t *>(blk + off_thr(QM));
+    // With two items per wave their dual parameters (2 (8 + 8 D) bytes, the
+    // two slots are consecutive) are staged in the wave's LDS region by one
+    // 16-byte load per lane, so the per-entry thresholds are LDS broadcasts
+    // instead of a chain of global loads.  The block array is padded past the
+    // last slot, so the second item's row is in bounds.
+    constexpr int TW = (int)(thr_bytes(QM) / 4);  // dwords per slot
+    __shared__ __align__(16) uint32_t sthr[4][LPI == 32 ? 2 * TW : 4];
+    const uint32_t *lthr = thr;
+    if constexpr (LPI == 32) {
+        uint32_t *my = sthr[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & 3];
+        const uint4 *src = reinterpret_cast<const uint4 *>(g.dparams + lm.base * thr_bytes(QM));
+        if (lm.lane < 1 + D) reinterpret_cast<uint4 *>(my)[lm.lane] = src[lm.lane];
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        lthr = my + (lm.lane >> 5) * TW + 2;
+    }
     const int De = UQ ? D : (qs - 1) * (qd - 1);
     const uint32_t ulo = (uint32_t)uid, uhi = (uint32_t)(uid >> 32);
     const uint64_t mact = __ballot(active);
@@ -445,7 +461,7 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
                 neg = __ballot(((sign >> dd) & 1ull) != 0);
             }
             const uint64_t yh = ya ^ neg;
-            const uint32_t tp8m1 = thr[2 * dd], tm8 = thr[2 * dd + 1];
+            const uint32_t tp8m1 = lthr[2 * dd], tm8 = lthr[2 * dd + 1];
             const uint64_t cp = __ballot(W[j] > tp8m1);          // U >= T+
             const uint64_t cm = __ballot(W[j] >= tm8);           // U >= T-
             const uint64_t ch = __ballot(W[j] >= 0x80000000u);   // U >= 2^23
