@@ -352,7 +352,9 @@ __device__ __forceinline__ void count_quad(uint32_t *__restrict__ counts, int64_
 // logic, and the ballot of theta is the dual bit-plane word.
 // UQ: every node has q_max states (compile-time entry loops).
 // ---------------------------------------------------------------------------
-template <int QM, int LPI, bool UQ>
+// STG: the caller is a launch of 256-thread blocks (four waves), so each wave
+// may stage its items' dual parameters in an LDS region of its own.
+template <int QM, int LPI, bool UQ, bool STG = false>
 __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const LaneMap<LPI> lm)
 {
     static_assert(LPI <= 32, "33 or more chains: k_dual64");
@@ -390,21 +392,28 @@ __device__ __forceinline__ void dual_wave(const Graph &g, uint32_t t, const Lane
     const uint8_t *blk = g.dparams + sl * thr_bytes(QM);
     const uint64_t sign = *reinterpret_cast<const uint64_t *>(blk);
     const uint32_t *thr = reinterpret_cast<const uint32_t *>(blk + off_thr(QM));
-    // With two items per wave their dual parameters (2 (8 + 8 D) bytes, the
-    // two slots are consecutive) are staged in the wave's LDS region by one
-    // 16-byte load per lane, so the per-entry thresholds are LDS broadcasts
-    // instead of a chain of global loads.  The block array is padded past the
-    // last slot, so the second item's row is in bounds.
+    // With 8 to 32 chains per item the dual parameters of the wave's P items
+    // (P (8 + 8 D) bytes; the slots are consecutive) are staged in the wave's
+    // LDS region by 16-byte loads, one or a few per lane, so the per-entry
+    // thresholds are LDS broadcasts instead of a chain of global loads.  The
+    // block array is padded to whole groups of 8 slots, so every item's row
+    // is in bounds.
     constexpr int TW = (int)(thr_bytes(QM) / 4);  // dwords per slot
-    __shared__ __align__(16) uint32_t sthr[4][LPI == 32 ? 2 * TW : 4];
+    constexpr bool STAGE = STG && LPI >= 8;
+    constexpr int NCH = P * (1 + D) / 2;           // 16-byte chunks of the P rows
+    __shared__ __align__(16) uint32_t sthr[4][STAGE ? P * TW : 4];
     const uint32_t *lthr = thr;
-    if constexpr (LPI == 32) {
+    if constexpr (STAGE) {
         uint32_t *my = sthr[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) & 3];
         const uint4 *src = reinterpret_cast<const uint4 *>(g.dparams + lm.base * thr_bytes(QM));
-        if (lm.lane < 1 + D) reinterpret_cast<uint4 *>(my)[lm.lane] = src[lm.lane];
+#pragma unroll
+        for (int i = 0; i < (NCH + 63) / 64; ++i) {
+            const int k = i * 64 + lm.lane;
+            if (k < NCH) reinterpret_cast<uint4 *>(my)[k] = src[k];
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        lthr = my + (lm.lane >> 5) * TW + 2;
+        lthr = my + (lm.lane / LPI) * TW + 2;
     }
     const int De = UQ ? D : (qs - 1) * (qd - 1);
     const uint32_t ulo = (uint32_t)uid, uhi = (uint32_t)(uid >> 32);
@@ -560,7 +569,7 @@ template <int QM, int LPI, bool UQ>
 __global__ __launch_bounds__(256) void k_dual(Graph g, uint32_t t)
 {
     sweep_args(g, t);
-    dual_wave<QM, LPI, UQ>(g, t, LaneMap<LPI>(g.C));
+    dual_wave<QM, LPI, UQ, true>(g, t, LaneMap<LPI>(g.C));
 }
 
 // ---------------------------------------------------------------------------
