@@ -83,6 +83,10 @@ struct pdg_ctx {
     uint32_t *d_hub = nullptr;   // hnode[nh] | hpfirst[nh + 1] | pnode[np] | pfirst[np] | pn[np]
     int64_t hub_cap = 0;         // u32 capacity of d_hub
     double *d_part = nullptr;    // [np][CB][QM - 1][64]
+    // node order of the chain-major primal (nodes by record count, largest
+    // first; rebuilt with the hub table)
+    uint32_t *d_order = nullptr;
+    bool order_set = false;
     int64_t part_cap = 0;        // doubles
     bool broken = false;         // an edit failed after it began to change the store
     void *d_static = nullptr;    // this device's copy of the static workspace (pdg_log_v_noalloc)
@@ -238,6 +242,7 @@ static Graph make_graph(pdg_ctx *ctx)
     g.C = ctx->C;
     g.CB = (int32_t)cdiv(ctx->C, 64);
     g.heavy = ctx->hub_thr;
+    g.order = ctx->order_set ? ctx->d_order : nullptr;
     g.k0 = (uint32_t)ctx->cfg.seed;
     g.k1 = (uint32_t)(ctx->cfg.seed >> 32);
     g.rk = make_round_keys(ctx->cfg.seed);
@@ -644,7 +649,9 @@ static size_t prim_bytes(int64_t m2, int64_t n)
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, d, k64, o64, (int)m2);
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, e, k64, o64, (int)n);
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, f, k, o, (int)n);
-    return std::max({a, b, c, d, e, f, (size_t)256});
+    size_t g = 0;
+    (void)hipcub::DeviceRadixSort::SortPairsDescending(nullptr, g, k, o, k, o, (int)n, 0, 16);
+    return std::max({a, b, c, d, e, f, g, (size_t)256});
 }
 
 template <int QM>
@@ -727,8 +734,8 @@ static pdg_status full_relayout(pdg_ctx *ctx, int64_t runs, const uint32_t *uniq
 // are split only while a hub piece kernel's LDS chunk holds at least the
 // records of one step (one record per lane group).  flag / pieces / hidx /
 // pidx: scratch of n entries.
-static pdg_status rebuild_hubs(pdg_ctx *ctx, uint32_t *flag, uint32_t *pieces, uint32_t *hidx,
-                               uint32_t *pidx, void *tmp, size_t tb)
+static pdg_status rebuild_hub_table(pdg_ctx *ctx, uint32_t *flag, uint32_t *pieces, uint32_t *hidx,
+                                    uint32_t *pidx, void *tmp, size_t tb)
 {
     ctx->hub_thr = 0;
     ctx->nh = ctx->np = 0;
@@ -774,6 +781,25 @@ static pdg_status rebuild_hubs(pdg_ctx *ctx, uint32_t *flag, uint32_t *pieces, u
     return PDG_OK;
 }
 
+// The hub table, then (chain-major primal) the node order: non-hub nodes by
+// record count, largest first, ties in id order, hubs last.  Scratch as for
+// rebuild_hub_table (tmp also holds a radix sort of n pairs).
+static pdg_status rebuild_hubs(pdg_ctx *ctx, uint32_t *flag, uint32_t *pieces, uint32_t *hidx,
+                               uint32_t *pidx, void *tmp, size_t tb)
+{
+    PDG_TRY(rebuild_hub_table(ctx, flag, pieces, hidx, pidx, tmp, tb));
+    if (!zc_layout(ctx->QM, ctx->C)) return PDG_OK;
+    const int64_t n = ctx->n;
+    const hipStream_t st = ctx->stream;
+    ctx->order_set = false;
+    k_order_keys<<<grid_for(n), 256, 0, st>>>(n, ctx->d_cnt, ctx->hub_thr, flag, hidx);
+    PDG_HIP(ctx, hipGetLastError());
+    PDG_HIP(ctx, hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, flag, pieces, hidx,
+                                                              ctx->d_order, (int)n, 0, 16, st));
+    ctx->order_set = true;
+    return PDG_OK;
+}
+
 // rebuild_hubs with scratch of its own (tuning, explicit settings)
 static pdg_status rebuild_hubs_alone(pdg_ctx *ctx)
 {
@@ -816,7 +842,7 @@ static void free_all(pdg_ctx *ctx)
                   ctx->d_off,   ctx->d_cnt,   ctx->d_pool,  ctx->d_rec_p,  ctx->d_rec_z,
                   ctx->d_flag,  ctx->d_scratch, ctx->d_base, ctx->d_hub, ctx->d_part,
                   ctx->d_free,  ctx->d_gen,   ctx->d_claim, ctx->d_cap,    ctx->d_nlive,
-                  ctx->d_mark,  ctx->d_sum,   ctx->d_lphi,  ctx->d_dparams};
+                  ctx->d_mark,  ctx->d_sum,   ctx->d_lphi,  ctx->d_dparams, ctx->d_order};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -910,6 +936,7 @@ pdg_status pdg_create(const pdg_config *cfg, int32_t device, void *stream, pdg_c
         (s = dalloc(ctx, (void **)&ctx->d_cap, N4 * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_nlive, N4 * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_mark, N4 * 4)) ||
+        (s = dalloc(ctx, (void **)&ctx->d_order, N4 * 4)) ||
         (s = dalloc(ctx, (void **)&ctx->d_sum, sizeof(EditSummary))))
         return bail(s);
     if (hipMemsetAsync(ctx->d_uid, 0, SP * 8, ctx->stream) != hipSuccess ||

@@ -96,6 +96,8 @@ struct Graph {
                                           // drawn by the hub kernels (0: none)
     uint32_t k0, k1;                      // generator key
     RoundKeys rk;                         // its ten round keys
+    const uint32_t *order;                // [n] node order of k_primal32z: its waves take the
+                                          // nodes in this order, four at a time (null: id order)
     const uint32_t *tsrc;                 // replayed sweeps: the sweep counter in device
                                           // memory (null: the kernel argument t)
     int64_t burn;                         // counting starts after this sweep (with tsrc)
@@ -1325,16 +1327,20 @@ __device__ __forceinline__ void add_tables(const double *__restrict__ tk, uint64
 }
 
 // ---------------------------------------------------------------------------
-// a4 + a5 with 17..32 chains and q_max >= 6 (chain-major dual words): one
-// node quad per wave, record group g = lane / 16 (chains l and l + 16 of
-// lane l of the group) takes node 4 Q + g and walks its records, one per
+// a4 + a5 with 17..32 chains and q_max >= 6 (chain-major dual words): four
+// nodes per wave, record group g = lane / 16 (chains l and l + 16 of lane l
+// of the group) takes the node at position 4 Q + g of the node order (nodes
+// sorted by record count, so the four take about as many steps; any order
+// draws the same values) and walks its records, one per
 // step, so a step takes up to four records, one per group.  A step's table
 // pairs are built into the wave's LDS region by the first 4 (QM-1) lanes
 // (lane (QM-1) g + r - 1 builds the pair of own state r of group g's record
 // from the h row it loaded) and read back by the group's lanes.  Loads run
 // through three register buffers, so while one step is processed the next
 // two are in flight.  No cross-group sum is needed and the four nodes are drawn
-// at once; a wave takes as many steps as its busiest node has records.
+// at once; a wave takes as many steps as its busiest node has records (in id
+// order 1.36 times the mean over a quad on a Chung-Lu graph of mean degree 8;
+// sorted, 1.00).
 // ---------------------------------------------------------------------------
 template <int QM, bool UQ, bool EXP64>
 __global__ __launch_bounds__(256) void k_primal32z(Graph g, uint32_t t, int count)
@@ -1352,9 +1358,19 @@ __global__ __launch_bounds__(256) void k_primal32z(Graph g, uint32_t t, int coun
     const int c1 = lane & 15, c2 = c1 + 16;
     const bool cv1 = c1 < g.C, cv2 = c2 < g.C;
     if (quad * 4 >= g.n) return;
-    // this group's node, and the table-building lane's node
-    const int64_t node = quad * 4 + grp;
-    const bool nin = node < g.n;
+    // the wave's four nodes: positions 4 Q .. 4 Q + 3 of the node order (nodes
+    // sorted by record count, so that they take about the same number of
+    // steps) or of the ids; group g takes the node at position 4 Q + g
+    uint32_t nd[4];
+    bool vin[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t pos = quad * 4 + j;
+        vin[j] = pos < g.n;
+        nd[j] = vin[j] ? (g.order ? g.order[pos] : (uint32_t)pos) : 0u;
+    }
+    const int64_t node = grp == 0 ? nd[0] : grp == 1 ? nd[1] : grp == 2 ? nd[2] : nd[3];
+    const bool nin = grp == 0 ? vin[0] : grp == 1 ? vin[1] : grp == 2 ? vin[2] : vin[3];
     const int kb = lane / S, rb = lane % S;  // builder: group kb, own state rb + 1
     const bool bl = lane < G * S;
     uint32_t cnt_g = 0, off_g = 0, cnt_b = 0, off_b = 0;
@@ -1363,8 +1379,8 @@ __global__ __launch_bounds__(256) void k_primal32z(Graph g, uint32_t t, int coun
         uint32_t cnt[4], off[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            off[j] = g.inc_off[quad * 4 + j];
-            cnt[j] = quad * 4 + j < g.n ? g.inc_cnt[quad * 4 + j] : 0u;
+            off[j] = g.inc_off[nd[j]];
+            cnt[j] = vin[j] ? g.inc_cnt[nd[j]] : 0u;
             if (g.heavy && cnt[j] > g.heavy) {
                 if (j == grp) hub_g = true;
                 cnt[j] = 0;
@@ -1441,35 +1457,30 @@ __global__ __launch_bounds__(256) void k_primal32z(Graph g, uint32_t t, int coun
         process(st + 2, hC, wC1, wC2);
         if (st + 5 < nsteps) issue(st + 5, hC, wC1, wC2);
     }
-    // draw: group g draws node 4 Q + g with word g of its chains' quad calls
-    const Words wq1 = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
-                                    (kPhasePrimal << 30) | (uint32_t)c1, t, g.rk);
-    const Words wq2 = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
-                                    (kPhasePrimal << 30) | (uint32_t)c2, t, g.rk);
+    // draw: a node i is drawn with word i mod 4 of its chains' calls on the
+    // node quad i / 4, wherever the order puts it
+    const uint32_t nq = (uint32_t)(node >> 2);
+    const Words wq1 = philox4x32_10(nq, 0u, (kPhasePrimal << 30) | (uint32_t)c1, t, g.rk);
+    const Words wq2 = philox4x32_10(nq, 0u, (kPhasePrimal << 30) | (uint32_t)c2, t, g.rk);
     const bool drawn = nin && !hub_g;
-    const int nx1 = draw_node<QM, UQ, EXP64>(L1, qn, word_at(wq1, grp) >> 8);
-    const int nx2 = draw_node<QM, UQ, EXP64>(L2, qn, word_at(wq2, grp) >> 8);
+    const int nx1 = draw_node<QM, UQ, EXP64>(L1, qn, word_at(wq1, (int)(node & 3)) >> 8);
+    const int nx2 = draw_node<QM, UQ, EXP64>(L2, qn, word_at(wq2, (int)(node & 3)) >> 8);
     if (drawn && cv1) g.x[node * g.C + c1] = (uint8_t)nx1;
     if (drawn && cv2) g.x[node * g.C + c2] = (uint8_t)nx2;
     if (count) {
-        // the wave owns the quad's counters (one chain block): row j QM + a
-        uint32_t *cq = g.counts + quad * 4 * QM;
-        uint32_t row = 0;
-        uint64_t wmask = 0;
+        // the wave owns its nodes' counters (one chain block): lane a of a
+        // group adds the group's draws of state a to its node's counter a
+        const uint32_t gsh = 16u * (uint32_t)grp;
+        uint32_t add = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-            for (int a = 0; a < QM; ++a) {
-                const bool mine = drawn && grp == j;
-                const uint32_t add = (uint32_t)__popcll(__ballot(mine && cv1 && nx1 == a)) +
-                                     (uint32_t)__popcll(__ballot(mine && cv2 && nx2 == a));
-                row = pdg_writelane_i32(cq[j * QM + a] + add, j * QM + a, row);
-            }
-            const uint64_t dj = __ballot(drawn && grp == j && lane == 16 * j);
-            const int qj = UQ ? QM : __shfl(qn, 16 * j);
-            if (dj) wmask |= ((1ull << qj) - 1ull) << (j * QM);
+        for (int a = 0; a < QM; ++a) {
+            const uint64_t b1 = __ballot(drawn && cv1 && nx1 == a);
+            const uint64_t b2 = __ballot(drawn && cv2 && nx2 == a);
+            const uint32_t na = (uint32_t)__popc((uint32_t)(b1 >> gsh) & 0xFFFFu) +
+                                (uint32_t)__popc((uint32_t)(b2 >> gsh) & 0xFFFFu);
+            if (c1 == a) add = na;
         }
-        if (lane_bit(wmask)) cq[lane] = row;
+        if (drawn && c1 < qn) g.counts[node * QM + c1] += add;
     }
 }
 

@@ -379,6 +379,18 @@ __global__ void k_hub_count(int64_t n, const uint32_t *__restrict__ cnt, uint32_
     pieces[i] = h ? (c + piece - 1) / piece : 0u;
 }
 
+// Sort keys of the node order of k_primal32z: the record count (hubs, drawn
+// by the hub kernels, 0), capped at 2^16 - 1; values the node ids.
+__global__ void k_order_keys(int64_t n, const uint32_t *__restrict__ cnt, uint32_t heavy,
+                             uint32_t *__restrict__ keys, uint32_t *__restrict__ ids)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c = cnt[i];
+    keys[i] = heavy && c > heavy ? 0u : (c < 0xFFFFu ? c : 0xFFFFu);
+    ids[i] = (uint32_t)i;
+}
+
 __global__ void k_hub_fill(int64_t n, const uint32_t *__restrict__ cnt, uint32_t piece,
                            const uint32_t *__restrict__ flag, const uint32_t *__restrict__ hidx,
                            const uint32_t *__restrict__ pidx, uint32_t nh, uint32_t np,
