@@ -1270,10 +1270,13 @@ __global__ __launch_bounds__(256) void k_primal32(Graph g, uint32_t t, int count
 // (record, r) the 16 sums over every subset of o = 1..4 (low nibble) and the
 // 8 over o = 5..7 (bits 4..6) are tabulated once per wave, so a chain adds
 // its field of state r with two table reads instead of QM-1 tests and FMAs.
-// Table pair of (record k, own state r): 24 doubles at (k (QM-1) + r-1) 24.
+// Table pair of (record k, own state r): 24 doubles at (k (QM-1) + r-1) 26.
+// One lane writes a pair with twelve 16-byte stores; a stride of 26 doubles
+// (52 dwords) puts the pairs of consecutive lanes in distinct LDS banks (at
+// 24, every other lane hit the same banks and the stores were serialised).
 // ---------------------------------------------------------------------------
 constexpr int kZChunk = 4;  // records per step of the chain-major hub pieces
-constexpr int kZPair = 24;  // doubles per (record, own state) table pair
+constexpr int kZPair = 26;  // doubles per (record, own state) table pair, 24 used
 
 // One table pair from the 2 h of o = 1..QM-1 (entries past QM-1 zero):
 // lo[m] = sum of the o = i+1 with bit i of m, i < 4; hi[m] likewise for o = i+5.
