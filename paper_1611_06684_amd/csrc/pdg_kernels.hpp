@@ -915,31 +915,58 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QM <= 5 ? 8
         }
         return shift;
     };
-    uint32_t shift[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) shift[j] = stage_chunk(j, 0, cnt[j] < K ? cnt[j] : K);
-    // mask lines of the four segments into L2 (lane (j, l): line l of node j)
     const int64_t zstride = (int64_t)g.CB * D * 2;  // u32 per record
-    uint32_t sink_z = 0;
-    {
-        const int j = lane >> 4, l = lane & 15;
-        const uint32_t oj = j == 0 ? off[0] : j == 1 ? off[1] : j == 2 ? off[2] : off[3];
-        const uint32_t cj = j == 0 ? cnt[0] : j == 1 ? cnt[1] : j == 2 ? cnt[2] : cnt[3];
-        const uint64_t zb = (uint64_t)oj * zstride * 4, ze = zb + (uint64_t)cj * zstride * 4;
-        const uint64_t za = (zb & ~(uint64_t)127) + 128 * (uint64_t)l;
-        if (za < ze)
-            sink_z = *reinterpret_cast<const uint32_t *>(
-                reinterpret_cast<const uint8_t *>(g.rec_z) + za);
-    }
-    // and the quad's base and counter rows (read later through scalar loads)
-    uint32_t sink_b = 0;
-    if (quad * 4 < g.n) {
-        // lanes 0..31: lines of the 32 QM base bytes; lanes 32..63: of the 16 QM counter bytes
-        const bool cpart = lane >= 32;
-        const uint64_t b0 = cpart ? (uint64_t)(g.counts + quad * 4 * QM) : (uint64_t)(g.base + quad * 4 * QM);
-        const uint64_t b1 = b0 + (cpart ? 16 * QM : 32 * QM);
-        const uint64_t ba = (b0 & ~(uint64_t)127) + 128 * (uint64_t)(lane & 31);
-        if (ba < b1 && (count || !cpart)) sink_b = *reinterpret_cast<const uint32_t *>(ba);
+    uint32_t sink_z, sink_b;  // touch loads, issued with the staging loads
+    // the first chunk of all four nodes: every lane loads its pieces of the
+    // four regions before any is written (lanes past a chunk's end re-read its
+    // first piece, in bounds as the record array is padded), so the four
+    // loads share one wait instead of one each.  Only when one of the nodes
+    // has a record: a context without edges has no record arrays at all.
+    uint32_t shift[4] = {0u, 0u, 0u, 0u};
+    sink_z = sink_b = 0u;
+    if ((cnt[0] | cnt[1] | cnt[2] | cnt[3]) != 0u) {
+        uint4 v[4][NLD];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t nrec = cnt[j] < K ? cnt[j] : K;
+            const uint64_t start = (uint64_t)off[j] * (RP * 8);
+            const uint64_t a16 = start & ~(uint64_t)15;
+            shift[j] = (uint32_t)(start - a16);
+            const uint32_t bytes = shift[j] + nrec * (RP * 8);
+            const uint8_t *src = reinterpret_cast<const uint8_t *>(g.rec_p) + a16;
+#pragma unroll
+            for (int i = 0; i < NLD; ++i) {
+                const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
+                v[j][i] = *reinterpret_cast<const uint4 *>(src + (o < bytes ? o : 0u));
+            }
+        }
+        // mask lines of the four segments into L2 (lane (j, l): line l of node
+        // j; lanes past a segment's end touch its first line again)
+        {
+            const int j = lane >> 4, l = lane & 15;
+            const uint32_t oj = j == 0 ? off[0] : j == 1 ? off[1] : j == 2 ? off[2] : off[3];
+            const uint32_t cj = j == 0 ? cnt[0] : j == 1 ? cnt[1] : j == 2 ? cnt[2] : cnt[3];
+            const uint64_t zb = (uint64_t)oj * zstride * 4, ze = zb + (uint64_t)cj * zstride * 4;
+            const uint64_t z0 = zb & ~(uint64_t)127, za = z0 + 128 * (uint64_t)l;
+            sink_z = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(g.rec_z) +
+                                                         (za < ze ? za : z0));
+        }
+        // and the quad's base and counter rows (read later through scalar loads;
+        // lanes 0..31: lines of the 32 QM base bytes, lanes 32..63: of the 16 QM
+        // counter bytes, or the base again when nothing is counted)
+        {
+            const int64_t qc = quad * 4 < g.n ? quad : 0;
+            const bool cpart = lane >= 32 && count;
+            const uint64_t b0 = cpart ? (uint64_t)(g.counts + qc * 4 * QM) : (uint64_t)(g.base + qc * 4 * QM);
+            const uint64_t b1 = b0 + (cpart ? 16 * QM : 32 * QM);
+            const uint64_t l0 = b0 & ~(uint64_t)127, ba = l0 + 128 * (uint64_t)(lane & 31);
+            sink_b = *reinterpret_cast<const uint32_t *>(ba < b1 ? ba : l0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < NLD; ++i)
+                *reinterpret_cast<uint4 *>(&stage[wib][j][(i * 64 + lane) * 16]) = v[j][i];
     }
     const Words wq = philox4x32_10((uint32_t)quad, (uint32_t)(quad >> 32),
                                    (kPhasePrimal << 30) | (uint32_t)lm.c, t, g.rk);
