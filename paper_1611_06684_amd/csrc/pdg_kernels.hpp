@@ -1510,7 +1510,8 @@ __global__ __launch_bounds__(256) void k_primal32z(Graph g, uint32_t t, int coun
                                 (uint32_t)__popc((uint32_t)(b2 >> gsh) & 0xFFFFu);
             if (c1 == a) add = na;
         }
-        if (drawn && c1 < qn) g.counts[node * QM + c1] += add;
+        // (an add without return: nothing waits on it; the wave owns the counter)
+        if (drawn && c1 < qn && add != 0u) atomicAdd(g.counts + node * QM + c1, add);
     }
 }
 
@@ -1845,7 +1846,8 @@ __device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int coun
         const bool active = nvalid && cvalid;
         if (active) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
         if (count) {
-            // one chain block: the lane group of the quad owns the node's counters
+            // one chain block: the lane group of the quad owns the node's
+            // counters (adds without return, so nothing waits on them)
             const bool leader = nvalid && (lm.lane % LPI == 0);
             const int p0 = (lm.lane / LPI) * LPI;
 #pragma unroll
@@ -1853,7 +1855,7 @@ __device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int coun
                 const uint64_t mine =
                     (__ballot(active && newx[j] == a) >> p0) & ((1ull << LPI) - 1ull);
                 if (leader && a < qnv[j] && mine != 0)
-                    g.counts[node * QM + a] += (uint32_t)__popcll(mine);
+                    atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(mine));
             }
         }
     }
@@ -1935,10 +1937,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UQ && QM <=
         const int qn = UQ ? QM : (drawn ? (int)g.q[node] : 0);
         newx[j] = -1;
         qnv[j] = 0;
+        // the base row is read by every lane (node 0's when the node is not
+        // drawn) and selected where it is used, so no load waits on a branch
         double L[QM];
+        const int64_t nb = drawn ? node : 0;
 #pragma unroll
-        for (int a = 0; a < QM; ++a)
-            L[a] = (drawn && (UQ || a < qn)) ? g.base[node * QM + a] : 0.0;
+        for (int a = 0; a < QM; ++a) {
+            const double b = g.base[nb * QM + a];
+            L[a] = (drawn && (UQ || a < qn)) ? b : 0.0;
+        }
         // each element's record index (in elements) and record count, from
         // the lanes of its quad
         uint64_t eb[NL];
@@ -1952,29 +1959,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UQ && QM <=
             ec[i] = epe[i] < 0 ? 0u : n;
         }
         const uint32_t mine = cnt[j];  // records of this lane's node j (0: hub, padding)
-        double vh[NL];
-        uint32_t vz[NL];
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            vh[i] = 0.0;
-            vz[i] = 0u;
-            if (ec[i] > 0) {
-                vh[i] = g.rec_p[eb[i]];
-                vz[i] = g.rec_z[eb[i]];
-            }
-        }
-        for (uint32_t k = 0; __ballot(k < mine) != 0; ++k) {
-            double nh[NL];
-            uint32_t nz[NL];
+        // Elements of step k, loaded unconditionally (an element without a
+        // record at step k reads element 0; no lane reads its row), into two
+        // buffers used in turn, so that step k + 1's loads stay in flight
+        // while step k is summed.  Only when some quad of the wave has a
+        // record: a context without edges has no record arrays.
+        auto issue = [&](uint32_t k, double (&vh)[NL], uint32_t (&vz)[NL]) {
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
-                nh[i] = 0.0;
-                nz[i] = 0u;
-                if (k + 1 < ec[i]) {
-                    nh[i] = g.rec_p[eb[i] + (uint64_t)(k + 1) * D];
-                    nz[i] = g.rec_z[eb[i] + (uint64_t)(k + 1) * D];
-                }
+                const uint64_t e = k < ec[i] ? eb[i] + (uint64_t)k * D : 0ull;
+                vh[i] = g.rec_p[e];
+                vz[i] = g.rec_z[e];
             }
+        };
+        auto step = [&](uint32_t k, const double (&vh)[NL], const uint32_t (&vz)[NL]) {
             // the previous step's reads are issued before these writes (LDS
             // operations of a wave complete in order)
             __builtin_amdgcn_wave_barrier();
@@ -2003,10 +2001,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UQ && QM <=
                     L[s] = acc;
                 }
             }
-#pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                vh[i] = nh[i];
-                vz[i] = nz[i];
+        };
+        if (__ballot(0u < mine) != 0) {
+            double ha[NL], hb[NL];
+            uint32_t za[NL], zb[NL];
+            issue(0, ha, za);
+            for (uint32_t k = 0;; k += 2) {
+                issue(k + 1, hb, zb);
+                step(k, ha, za);
+                if (__ballot(k + 1 < mine) == 0) break;
+                issue(k + 2, ha, za);
+                step(k + 1, hb, zb);
+                if (__ballot(k + 2 < mine) == 0) break;
             }
         }
         if (drawn) {
@@ -2021,7 +2027,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UQ && QM <=
         const bool active = nvalid && cvalid;
         if (active) g.x[node * g.C + lm.c] = (uint8_t)newx[j];
         if (count) {
-            // one chain block: the lane group of the quad owns the node's counters
+            // one chain block: the lane group of the quad owns the node's
+            // counters (adds without return, so nothing waits on them)
             const bool leader = nvalid && (lane % LPI == 0);
             const int p0 = p * LPI;
 #pragma unroll
@@ -2029,7 +2036,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UQ && QM <=
                 const uint64_t mine =
                     (__ballot(active && newx[j] == a) >> p0) & ((1ull << LPI) - 1ull);
                 if (leader && a < qnv[j] && mine != 0)
-                    g.counts[node * QM + a] += (uint32_t)__popcll(mine);
+                    atomicAdd(g.counts + node * QM + a, (uint32_t)__popcll(mine));
             }
         }
     }
