@@ -756,21 +756,26 @@ static pdg_status rebuild_hub_table(pdg_ctx *ctx, uint32_t *flag, uint32_t *piec
     PDG_TRY(read_sum(ctx, &h));
     const int64_t nh = h.nh, np = h.np;
     if (nh == 0) return PDG_OK;
+    // both grow with half again as much room, so that a hub list that
+    // changes a little from one edit batch to the next does not reallocate
+    // (a free waits for the device)
     const int64_t words = nh + (nh + 1) + 3 * np;
     if (words > ctx->hub_cap) {
         if (ctx->d_hub) PDG_HIP(ctx, hipFree(ctx->d_hub));
         ctx->d_hub = nullptr;
         ctx->hub_cap = 0;
-        PDG_TRY(dalloc(ctx, (void **)&ctx->d_hub, words * 4));
-        ctx->hub_cap = words;
+        const int64_t cap = words + words / 2 + 256;
+        PDG_TRY(dalloc(ctx, (void **)&ctx->d_hub, cap * 4));
+        ctx->hub_cap = cap;
     }
     const int64_t pd = np * ctx->CB * (ctx->QM - 1) * 64;
     if (pd > ctx->part_cap) {
         if (ctx->d_part) PDG_HIP(ctx, hipFree(ctx->d_part));
         ctx->d_part = nullptr;
         ctx->part_cap = 0;
-        PDG_TRY(dalloc(ctx, (void **)&ctx->d_part, pd * 8));
-        ctx->part_cap = pd;
+        const int64_t cap = pd + pd / 2 + 4096;
+        PDG_TRY(dalloc(ctx, (void **)&ctx->d_part, cap * 8));
+        ctx->part_cap = cap;
     }
     k_hub_fill<<<grid_for(n), 256, 0, st>>>(n, ctx->d_cnt, ctx->tune_piece, flag, hidx, pidx,
                                             (uint32_t)nh, (uint32_t)np, ctx->d_hub);

@@ -2355,13 +2355,34 @@ __global__ __launch_bounds__(256) void k_node_base(int64_t nn, const uint32_t *_
 #pragma unroll
     for (int a = 0; a < QM; ++a) acc[a] = 0.0;
     const uint32_t o = off[i], n = cnt[i];
-    for (uint32_t r = lane; r < n; r += 64) {
-        const uint32_t e = inc[o + r];
-        if (e == kTomb) continue;
-        const double *c0 = reinterpret_cast<const double *>(
-            params + (int64_t)(e >> 1) * block_bytes(QM) + off_c0(QM));
+    // a lane adds its records r = lane, lane + 64, ... in that order; four at
+    // a time, with every load issued before any is used (entries past the end
+    // re-read the last one, tombstones read block 0, and both add nothing),
+    // so a hub's wave waits once per four records instead of once per record
+    constexpr int U = 4;
+    for (uint32_t r0 = lane; r0 < n; r0 += 64 * U) {
+        uint32_t e[U];
 #pragma unroll
-        for (int a = 1; a < QM; ++a) acc[a] += c0[(e & 1u) * (QM - 1) + (a - 1)];
+        for (int u = 0; u < U; ++u) {
+            const uint32_t r = r0 + 64u * u;
+            const uint32_t v = inc[o + (r < n ? r : n - 1u)];
+            e[u] = r < n ? v : kTomb;
+        }
+        double c[U][QM - 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool live = e[u] != kTomb;
+            const double *c0 = reinterpret_cast<const double *>(
+                params + (live ? (int64_t)(e[u] >> 1) * block_bytes(QM) : 0) + off_c0(QM));
+            const uint32_t side = live ? (e[u] & 1u) : 0u;
+#pragma unroll
+            for (int a = 1; a < QM; ++a) c[u][a - 1] = c0[side * (QM - 1) + (a - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e[u] != kTomb)
+#pragma unroll
+                for (int a = 1; a < QM; ++a) acc[a] += c[u][a - 1];
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1)
