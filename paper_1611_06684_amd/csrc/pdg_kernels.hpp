@@ -980,10 +980,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QM <= 5 ? 8
         if (node >= g.n || ((hub >> j) & 1u)) continue;
         const int qn = UQ ? QM : (int)g.q[node];
         qnv[j] = qn;
-        // the theta-free part (lam and every c0) is the node's base
+        // the theta-free part (lam and every c0) is the node's base, read by
+        // vector loads from an opaque copy of the node id (an identity DPP
+        // move), so that its latency overlaps the first mask loads' wait
+        // instead of adding a scalar wait of its own
+        const int64_t nv = (int64_t)(uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)node, 0xE4, 0xF, 0xF, false);
         double L[QM];
 #pragma unroll
-        for (int a = 0; a < QM; ++a) L[a] = (UQ || a < qn) ? g.base[node * QM + a] : 0.0;
+        for (int a = 0; a < QM; ++a) L[a] = (UQ || a < qn) ? g.base[nv * QM + a] : 0.0;
         auto record = [&](const double *h, const uint64_t *z) {
 #pragma unroll
             for (int s = 1; s < QM; ++s) {
