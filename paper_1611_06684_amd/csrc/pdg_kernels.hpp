@@ -1571,28 +1571,36 @@ __global__ __launch_bounds__(256) void k_hub_pieces(Graph g, int64_t np,
     if (lane < ZB / 16)
         *reinterpret_cast<uint4 *>(reg + BUF - ZB + 16 * lane) = make_uint4(0, 0, 0, 0);
     const uint32_t *zero = reinterpret_cast<const uint32_t *>(reg + BUF - ZB);
-    auto copy16 = [&](const uint8_t *src, uint64_t a, uint32_t nb, uint32_t dst) -> uint32_t {
-        const uint64_t a16 = a & ~(uint64_t)15;
-        const uint32_t shift = (uint32_t)(a - a16);
-        const uint32_t bytes = shift + nb;
-#pragma unroll
-        for (int i = 0; i < NLD; ++i) {
-            const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
-            if (o < bytes)
-                *reinterpret_cast<uint4 *>(reg + dst + o) =
-                    *reinterpret_cast<const uint4 *>(src + a16 + o);
-        }
-        return shift;
-    };
     double L[QM];
 #pragma unroll
     for (int a = 0; a < QM; ++a) L[a] = 0.0;
     for (uint32_t first = 0; first < n; first += K) {
         const uint32_t nrec = min(n - first, K);
-        const uint32_t sh = copy16(reinterpret_cast<const uint8_t *>(g.rec_p),
-                                   (r0 + first) * (RP * 8), nrec * (RP * 8), 0);
-        const uint32_t sz = copy16(reinterpret_cast<const uint8_t *>(g.rec_z),
-                                   (r0 + first) * zr * 4, nrec * zr * 4, HB);
+        // the chunk's h rows (to 0) and mask words (to HB) in 16-byte aligned
+        // pieces: every lane loads its pieces of both without a branch (pieces
+        // past the end re-read the first, which lies in the chunk's first
+        // record) and writes them, a piece past the end to the first piece's
+        // place with the first piece's bytes, so no load is moved into a
+        // branch and all of a chunk's loads share one wait
+        const uint64_t ah = (r0 + first) * (RP * 8), az = (r0 + first) * zr * 4;
+        const uint64_t ah16 = ah & ~(uint64_t)15, az16 = az & ~(uint64_t)15;
+        const uint32_t sh = (uint32_t)(ah - ah16), sz = (uint32_t)(az - az16);
+        const uint32_t bh = sh + nrec * (RP * 8), bz = sz + nrec * zr * 4;
+        const uint8_t *ph = reinterpret_cast<const uint8_t *>(g.rec_p) + ah16;
+        const uint8_t *pz = reinterpret_cast<const uint8_t *>(g.rec_z) + az16;
+        uint4 vh[NLD], vz[NLD];
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
+            vh[i] = *reinterpret_cast<const uint4 *>(ph + (o < bh ? o : 0u));
+            vz[i] = *reinterpret_cast<const uint4 *>(pz + (o < bz ? o : 0u));
+        }
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const uint32_t o = (uint32_t)(i * 64 + lane) * 16;
+            *reinterpret_cast<uint4 *>(reg + (o < bh ? o : 0u)) = vh[i];
+            *reinterpret_cast<uint4 *>(reg + HB + (o < bz ? o : 0u)) = vz[i];
+        }
         const double *hs = reinterpret_cast<const double *>(reg + sh);
         const uint32_t *zs = reinterpret_cast<const uint32_t *>(reg + HB + sz);
         for (uint32_t k = 0; k < nrec; k += PR) {
