@@ -1834,7 +1834,7 @@ __device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int coun
         for (int a = 0; a < QM; ++a) L[a] = (UQ || a < qn) ? g.base[node * QM + a] : 0.0;
         const double *hp = g.rec_p + (uint64_t)off[j] * RP;
         const uint32_t *zp = g.rec_z + (uint64_t)off[j] * D;
-        for (uint32_t k = 0; k < cnt[j]; ++k, hp += RP, zp += D) {
+        auto add_record = [&](const double (&h)[D], const uint32_t (&z)[D]) {
 #pragma unroll
             for (int s = 1; s < QM; ++s) {
                 if (!UQ && s >= qn) break;
@@ -1843,10 +1843,44 @@ __device__ __forceinline__ void primal_wave(const Graph &g, uint32_t t, int coun
                 for (int o = 1; o < QM; ++o) {
                     // acc + 2 theta h in one FMA: the factor is 0.0 or 2.0 and 2 h is exact
                     const int dp = (s - 1) * (QM - 1) + (o - 1);
-                    const bool th = ((zp[dp] >> (lm.c & 31)) & 1u) != 0;
-                    acc = __builtin_fma(__hiloint2double(th ? 0x40000000 : 0, 0), hp[dp], acc);
+                    const bool th = ((z[dp] >> (lm.c & 31)) & 1u) != 0;
+                    acc = __builtin_fma(__hiloint2double(th ? 0x40000000 : 0, 0), h[dp], acc);
                 }
                 L[s] = acc;
+            }
+        };
+        if constexpr (D <= 9) {
+            // two records per step, both loaded before either is added (the
+            // second index stays on the last record past the end), so a lane
+            // waits once per two records; the sums keep record order
+            for (uint32_t k = 0; k < cnt[j]; k += 2) {
+                const uint32_t k1 = k + 1 < cnt[j] ? k + 1 : k;
+                double h0[D], h1[D];
+                uint32_t z0[D], z1[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    h0[d] = hp[(uint64_t)k * RP + d];
+                    z0[d] = zp[(uint64_t)k * D + d];
+                    h1[d] = hp[(uint64_t)k1 * RP + d];
+                    z1[d] = zp[(uint64_t)k1 * D + d];
+                }
+                add_record(h0, z0);
+                if (k + 1 < cnt[j]) add_record(h1, z1);
+            }
+        } else {
+            for (uint32_t k = 0; k < cnt[j]; ++k, hp += RP, zp += D) {
+#pragma unroll
+                for (int s = 1; s < QM; ++s) {
+                    if (!UQ && s >= qn) break;
+                    double acc = L[s];
+#pragma unroll
+                    for (int o = 1; o < QM; ++o) {
+                        const int dp = (s - 1) * (QM - 1) + (o - 1);
+                        const bool th = ((zp[dp] >> (lm.c & 31)) & 1u) != 0;
+                        acc = __builtin_fma(__hiloint2double(th ? 0x40000000 : 0, 0), hp[dp], acc);
+                    }
+                    L[s] = acc;
+                }
             }
         }
         newx[j] = draw_node<QM, UQ, EXP64>(L, qn, Wn[j] >> 8);
